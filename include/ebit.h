@@ -1,0 +1,158 @@
+/*
+ * ebit.h -- C ABI of the MI355X library for the hot path of the 3D
+ * Edge-Based Interface Tracking method (Pan, Long, Scardovelli, Popinet,
+ * Zaleski, arXiv 2509.26361): direction-split interface advection and the
+ * Front2VOF volume fraction on a uniform periodic grid.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: n^3 cells of size h = 1/n, periodic, n a multiple of 4 and >= 8.
+ * Node (i,j,k) has linear index i + n*(j + n*k) (x fastest); every array
+ * below has n^3 entries in that order.
+ *
+ * State (sec. 2.3, Fig. 6b: one edge field, one vertex field, one face
+ * field), per node:
+ *   flags bit 0     colour of node (i,j,k): 1 = reference phase (sec. 2.2)
+ *   flags bit 1+a   colour at the centre of the face with normal axis a whose
+ *                   lowest corner is node (i,j,k) (sec. 2.3, 2.4)
+ *   flags bit 4+e   a marker lies on the edge along axis e that starts at node
+ *                   (i,j,k); at most one per edge, present iff the two end
+ *                   colours differ (sec. 2.2)
+ *   s_e             the marker's fraction along that edge, in [0, 1 - 2^-52]
+ *                   (0 where there is none); double, or float in EBIT_FP32
+ * Memory: all array pointers are DEVICE pointers owned by the caller; the
+ * library never allocates or frees state memory.  Work space comes from the
+ * caller's `scratch` buffer (ebit_scratch_bytes).  The context is a small
+ * host object.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream); every call is
+ * asynchronous on it unless stated otherwise.
+ * Errors: entry points return EBIT_OK (0) or a negative code; argument errors
+ * are detected on the host before anything is enqueued.  Conditions found on
+ * the device (Courant number above one) are reported by ebit_stats.
+ * Threads: one context per host thread at a time.
+ */
+#ifndef EBIT_H
+#define EBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EBIT_OK = 0,
+    EBIT_EINVAL = -1,   /* bad argument (null pointer, n, direction, size) */
+    EBIT_ECFL = -2,     /* |Courant number| > 1 somewhere (sec. 2.3: CFL <= 1) */
+    EBIT_ESTATE = -3,   /* inconsistent state */
+    EBIT_EHIP = -4,     /* a HIP runtime call failed */
+    EBIT_ENOSURR = -5,  /* surrogate weights missing */
+    EBIT_ESCRATCH = -6  /* scratch buffer too small */
+};
+
+enum { EBIT_FP64 = 0, EBIT_FP32 = 1 };
+
+typedef struct ebit_ctx ebit_ctx;
+
+/* Description of the caller's buffers.  The state is double-buffered: each
+ * sweep reads buffer ebit_current() and writes the other one. */
+typedef struct {
+    int32_t n;              /* cells per axis */
+    int32_t precision;      /* EBIT_FP64: s_e, U, C are double; EBIT_FP32: float */
+    void *s[2][3];          /* s[buffer][axis]: marker fractions, n^3 each */
+    uint8_t *flags[2];      /* flags[buffer]: n^3 bytes each */
+    void *scratch;          /* device work space, >= ebit_scratch_bytes(n) bytes */
+    size_t scratch_bytes;
+} ebit_desc;
+
+/* Bytes of device scratch the library needs for an n^3 grid. */
+size_t ebit_scratch_bytes(int32_t n);
+
+/*
+ * Create a context over the caller's buffers and initialise state buffer 0
+ * from a sampled interface (sec. 3.1): node colour = [phi > 0]; where an
+ * edge's end colours differ its marker sits at the linear zero of phi,
+ * s = phi_a / (phi_a - phi_b), or at s_exact[e] if s_exact is not NULL (the
+ * exact crossing, a test mode).  Face-centre colour = [phi_faces[a] > 0] on
+ * faces that carry markers, the corner colour on faces that carry none.
+ *   phi_nodes    device, n^3 doubles, or NULL: buffer 0 already holds a state
+ *                (e.g. a checkpoint) and only the work lists are built
+ *   phi_faces    3 device pointers (n^3 doubles each), required with phi_nodes
+ *   s_exact      NULL or 3 device pointers (n^3 doubles each)
+ * Returns EBIT_EINVAL / EBIT_ESCRATCH on bad arguments; *out is set only on
+ * success.  Enqueued on `stream`.
+ */
+int ebit_init(ebit_ctx **out, const ebit_desc *desc, const double *phi_nodes,
+              const double *const *phi_faces, const double *const *s_exact, void *stream);
+
+/*
+ * One one-dimensional advection sweep along axis `dir` (0 = x, 1 = y, 2 = z),
+ * secs. 2.1-2.4: every marker moves by an explicit Euler step (eq.
+ * Eq_marker_dis) with displacement (dt/h) * g * u in cell units, u the
+ * node velocity U_dir interpolated linearly along the marker's own edge;
+ * node colours flip where markers cross nodes (Fig. 4); markers on edges
+ * along `dir` land on the edge they reach, pairs annihilating (Fig. 5a);
+ * markers on the other edges are replaced by the crossings of the advected
+ * interface with the grid lines, placed by the circle fit of sec. 2.1 on the
+ * two face families that contain `dir`; the face-centre colours of those two
+ * families are recomputed.  Reads buffer ebit_current(), writes the other one
+ * and makes it current.
+ *   U_dir   device, n^3 doubles (floats in EBIT_FP32): the `dir` component of
+ *           the velocity's spatial factor at the nodes
+ *   g, dt   time factor and time step; |(dt n) g U| must stay <= 1
+ *           (otherwise the result is undefined and ebit_stats reports
+ *           EBIT_ECFL).
+ */
+int ebit_advect_sweep(ebit_ctx *ctx, int dir, const void *U_dir, double g, double dt, void *stream);
+
+/*
+ * Front2VOF (sec. 2.5): reference-phase volume fraction of every cell from
+ * the current state: face segments (paired by the face-centre colour on
+ * faces with four markers), closed loops, loop centroid, fan of triangles,
+ * enclosed volume by Gauss's theorem.
+ *   C       device, n^3 doubles (floats in EBIT_FP32).  Only cells whose
+ *           state may have changed since the previous call with the same C
+ *           are rewritten; a different C pointer is filled completely.
+ */
+int ebit_front2vof(ebit_ctx *ctx, void *C, void *stream);
+
+typedef struct {
+    double volume;          /* sum of C over all cells (compensated, FP64) */
+    double volume_comp;     /* its compensation term: volume + volume_comp */
+    int64_t n_interfacial;  /* cells with a marker on any of their 12 edges, at the last ebit_front2vof */
+    int64_t n_ambiguous;    /* of those: a face with 4 markers or more than one loop */
+    int64_t n_markers[3];   /* markers per edge family in the current state */
+    int64_t n_fallback;     /* sweeps so far: edges placed by the no-crossing fallback */
+    int64_t n_multi;        /* sweeps so far: new unaligned markers with > 1 crossing */
+    int64_t n_cfl;          /* sweeps so far: markers moved by more than one cell */
+    int64_t n_merged;       /* sweeps so far: aligned edges reached by > 1 marker */
+    int64_t n_active_cells; /* cells processed by the last sweep (work-list size) */
+    int64_t step_sweeps;    /* sweeps so far */
+} ebit_stats_t;
+
+/*
+ * Statistics of the current state and of C (the array last passed to
+ * ebit_front2vof).  Synchronises `stream`.  Returns EBIT_ECFL if any sweep
+ * so far broke the Courant limit, else EBIT_OK.
+ */
+int ebit_stats(ebit_ctx *ctx, const void *C, ebit_stats_t *out, void *stream);
+
+/* Index (0 or 1) of the state buffer holding the current state. */
+int ebit_current(const ebit_ctx *ctx);
+
+/* Option switches. */
+enum { EBIT_OPT_FULL_GRID = 1 };   /* 1: process every cell, not only the band */
+int ebit_set_option(ebit_ctx *ctx, int option, int value);
+
+/* Free the context (not the caller's buffers). */
+void ebit_destroy(ebit_ctx *ctx);
+
+/* Static message for an error code. */
+const char *ebit_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBIT_H */

@@ -259,9 +259,13 @@ static double line_cross(double X0, double P2x, double P2y, double P3x, double P
 
 /* Circle through T, P2, P3 (sec. 2.1, Fig. 2) and its intersection with the
  * line X = 0 that lies on the arc from P2 to P3 not containing T.  P2 is left
- * of the line and P3 on or right of it, so the chord crosses the line between
- * the two roots; the wanted root is on the other side of the chord from T:
- * the lower root when T is left of P2->P3 (D > 0), the upper one otherwise.
+ * of the line and P3 right of it, so the chord crosses the line between the
+ * two roots; the wanted root is on the other side of the chord from T: the
+ * lower root when T is left of P2->P3 (D > 0), the upper one otherwise.
+ * With u the centre relative to P2 and x0 = -P2x the line relative to P2, the
+ * roots are P2y + t with t = u_y -+ sqrt(u_y^2 - w), w = x0 (x0 - 2 u_x); the
+ * root nearer P2 is taken in the conjugate form w / (u_y +- sqrt(.)) so large
+ * nearly straight circles keep their accuracy.
  * Returns 0 (a straight line, infinite radius) when the points are collinear
  * or the radius exceeds 1e6 cells (READING: threshold). */
 static int circle_root(double Tx, double Ty, double P2x, double P2y, double P3x, double P3y,
@@ -277,11 +281,18 @@ static int circle_root(double Tx, double Ty, double P2x, double P2y, double P3x,
     double uy = (bx * C2 - cx * B2) / D;
     double r2 = ux * ux + uy * uy;
     if (!(r2 < 1e12)) return 0;
-    double ox = P2x + ux, oy = P2y + uy;
-    double disc = r2 - ox * ox;
-    if (disc < 0.0) disc = 0.0;
-    double sq = sqrt(disc);
-    *root = D > 0.0 ? oy - sq : oy + sq;
+    double x0 = -P2x;
+    double w = x0 * (x0 - 2.0 * ux);
+    double q = uy * uy - w;
+    double t;
+    if (!(q > 0.0)) {
+        t = uy;                                   /* tangent */
+    } else {
+        double sq = sqrt(q);
+        if (D > 0.0) t = uy > 0.0 ? w / (uy + sq) : uy - sq;    /* lower root */
+        else t = uy < 0.0 ? w / (uy - sq) : uy + sq;            /* upper root */
+    }
+    *root = P2y + t;
     *r2out = r2;
     return 1;
 }

@@ -1,0 +1,212 @@
+"""Thin Python binding of the C ABI in ``include/ebit.h`` (argument
+marshalling only: every step of the hot path runs in the HIP library).
+
+PyTorch provides device memory and streams.  The binding fails loudly if the
+built library is missing; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebit.so")
+
+EBIT_OK, EBIT_EINVAL, EBIT_ECFL, EBIT_ESTATE, EBIT_EHIP, EBIT_ENOSURR, EBIT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+EBIT_FP64, EBIT_FP32 = 0, 1
+EBIT_OPT_FULL_GRID = 1
+
+_lib = None
+
+
+class EbitError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("s", (ctypes.c_void_p * 3) * 2),
+        ("flags", ctypes.c_void_p * 2),
+        ("scratch", ctypes.c_void_p),
+        ("scratch_bytes", ctypes.c_size_t),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("volume", ctypes.c_double),
+        ("volume_comp", ctypes.c_double),
+        ("n_interfacial", ctypes.c_int64),
+        ("n_ambiguous", ctypes.c_int64),
+        ("n_markers", ctypes.c_int64 * 3),
+        ("n_fallback", ctypes.c_int64),
+        ("n_multi", ctypes.c_int64),
+        ("n_cfl", ctypes.c_int64),
+        ("n_merged", ctypes.c_int64),
+        ("n_active_cells", ctypes.c_int64),
+        ("step_sweeps", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["n_markers"] = list(self.n_markers)
+        return d
+
+
+def lib():
+    """Load ``libebit.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python -m paper_2509_26361_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.ebit_scratch_bytes.argtypes = [ctypes.c_int32]
+        L.ebit_scratch_bytes.restype = ctypes.c_size_t
+        L.ebit_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Desc), P, P, P, P]
+        L.ebit_init.restype = ctypes.c_int
+        L.ebit_advect_sweep.argtypes = [P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P]
+        L.ebit_advect_sweep.restype = ctypes.c_int
+        L.ebit_front2vof.argtypes = [P, P, P]
+        L.ebit_front2vof.restype = ctypes.c_int
+        L.ebit_stats.argtypes = [P, P, ctypes.POINTER(Stats), P]
+        L.ebit_stats.restype = ctypes.c_int
+        L.ebit_current.argtypes = [P]
+        L.ebit_current.restype = ctypes.c_int
+        L.ebit_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        L.ebit_set_option.restype = ctypes.c_int
+        L.ebit_destroy.argtypes = [P]
+        L.ebit_destroy.restype = None
+        L.ebit_strerror.argtypes = [ctypes.c_int]
+        L.ebit_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().ebit_strerror(int(code)).decode()
+    except Exception:  # library missing: still format the error
+        return "error"
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ptr_array(ts):
+    if ts is None:
+        return None
+    arr = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+class Ebit:
+    """An EBIT state on one GPU: two state buffers, scratch and a context."""
+
+    def __init__(self, n: int, precision: str = "fp64", device="cuda"):
+        if n < 8 or n % 4:
+            raise ValueError("n must be a multiple of 4 and >= 8")
+        self.n = n
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device(device)
+        shape = (n, n, n)
+        self.flags = [torch.zeros(shape, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.s = [[torch.zeros(shape, dtype=self.dtype, device=self.device) for _ in range(3)] for _ in range(2)]
+        nbytes = lib().ebit_scratch_bytes(n)
+        self.scratch = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p(None)
+        d = Desc()
+        d.n = n
+        d.precision = EBIT_FP64 if precision == "fp64" else EBIT_FP32
+        for b in range(2):
+            for e in range(3):
+                d.s[b][e] = self.s[b][e].data_ptr()
+            d.flags[b] = self.flags[b].data_ptr()
+        d.scratch = self.scratch.data_ptr()
+        d.scratch_bytes = nbytes
+        self._desc = d
+
+    # -- state ---------------------------------------------------------------
+    def init(self, phi_nodes, phi_faces, s_exact=None, stream=None):
+        """Markers and colours from sampled phi (device float64 tensors)."""
+        self._destroy()
+        pf, keep_pf = _ptr_array(phi_faces)
+        se = _ptr_array(s_exact)
+        rc = lib().ebit_init(ctypes.byref(self.ctx), ctypes.byref(self._desc), _ptr(phi_nodes), pf,
+                             se[0] if se else None, _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_init")
+        return self
+
+    def load_state(self, flags, s, stream=None):
+        """Start from a given state (e.g. a checkpoint): copies into buffer 0."""
+        self._destroy()
+        self.flags[0].copy_(flags)
+        for e in range(3):
+            self.s[0][e].copy_(s[e])
+        rc = lib().ebit_init(ctypes.byref(self.ctx), ctypes.byref(self._desc), None, None, None, _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_init")
+        return self
+
+    def current(self):
+        return lib().ebit_current(self.ctx)
+
+    def state(self):
+        """(flags, [s_x, s_y, s_z]) of the current buffer (views)."""
+        c = self.current()
+        return self.flags[c], self.s[c]
+
+    def set_option(self, option, value):
+        rc = lib().ebit_set_option(self.ctx, option, int(value))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_set_option")
+
+    # -- hot path ------------------------------------------------------------
+    def sweep(self, d: int, U, g: float, dt: float, stream=None):
+        rc = lib().ebit_advect_sweep(self.ctx, int(d), _ptr(U), float(g), float(dt), _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_advect_sweep")
+
+    def step(self, Uxyz, g: float, dt: float, order=(0, 1, 2), stream=None):
+        for d in order:
+            self.sweep(d, Uxyz[d], g, dt, stream)
+
+    def front2vof(self, C, stream=None):
+        rc = lib().ebit_front2vof(self.ctx, _ptr(C), _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_front2vof")
+        return C
+
+    def stats(self, C, stream=None, check_cfl=True):
+        st = Stats()
+        rc = lib().ebit_stats(self.ctx, _ptr(C), ctypes.byref(st), _stream(stream))
+        if rc not in (EBIT_OK, EBIT_ECFL) or (check_cfl and rc == EBIT_ECFL):
+            raise EbitError(rc, "ebit_stats")
+        return st.as_dict()
+
+    def _destroy(self):
+        if self.ctx:
+            lib().ebit_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self._destroy()
+        except Exception:
+            pass

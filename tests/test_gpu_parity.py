@@ -1,0 +1,238 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle:
+colours, face colours and marker existence bit-exact; marker positions and
+volume fractions within 1e-12 (FP64)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_26361_amd import ebit as E
+from paper_2509_26361_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def T(a, d=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(d or dev())
+
+
+def gpu_init(sh, exact=False, precision="fp64"):
+    n = sh.n
+    e = E.Ebit(n, precision, dev())
+    e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces], [T(x) for x in sh.s_exact] if exact else None)
+    return e
+
+
+def gpu_from_oracle(st, precision="fp64"):
+    e = E.Ebit(st.n, precision, dev())
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    e.load_state(T(st.flags), [T(x).to(dt) for x in st.s])
+    return e
+
+
+def compare_state(e, st, tol=TOL, what=""):
+    torch.cuda.synchronize()
+    fl, s = e.state()
+    f = fl.cpu().numpy()
+    bad = np.argwhere(f != st.flags)
+    assert len(bad) == 0, f"{what}: {len(bad)} flag mismatches, first at {bad[:3].tolist()} " \
+                          f"gpu={f[tuple(bad[0])]:#x} oracle={st.flags[tuple(bad[0])]:#x}"
+    for k in range(3):
+        d = np.max(np.abs(s[k].cpu().numpy().astype(np.float64) - st.s[k]))
+        assert d <= tol, f"{what}: s[{k}] differs by {d}"
+
+
+def compare_C(C, Co, tol=TOL, what=""):
+    torch.cuda.synchronize()
+    d = np.max(np.abs(C.cpu().numpy().astype(np.float64) - Co))
+    assert d <= tol, f"{what}: C differs by {d}"
+
+
+@pytest.mark.parametrize("case", ["sphere_linear", "sphere_exact", "random"])
+def test_init_parity(case):
+    if case == "random":
+        sh, exact = I.random_shape(16, 1), True
+    else:
+        sh, exact = I.sphere_shape(32), case == "sphere_exact"
+    st = O.init(sh, exact=exact)
+    e = gpu_init(sh, exact)
+    compare_state(e, st, 0.0, case)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("full", [0, 1])
+def test_single_sweep_parity_random_states(seed, full):
+    """Arbitrary states (saddles, 4-marker faces, thin necks) under a random
+    smooth velocity with |lambda u| <= 1, one sweep per direction from the same
+    oracle state; band and full-grid processing."""
+    n = 16 if seed < 3 else 20
+    st = O.init(I.random_shape(n, seed + 10), exact=True)
+    U = I.fourier_velocity(n, seed=seed + 20, modes=4)
+    for d in range(3):
+        e = gpu_from_oracle(st)
+        e.set_option(E.EBIT_OPT_FULL_GRID, full)
+        e.sweep(d, T(U[d]), 1.0, 1.0 / n)
+        st2, cnt = O.sweep(st, d, 1.0, 1.0 / n, U[d])
+        compare_state(e, st2, TOL, f"seed {seed} dir {d} full {full}")
+        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        e.front2vof(C)
+        Co, amb = O.f2v(st2)
+        compare_C(C, Co, TOL, f"seed {seed} dir {d}")
+        s = e.stats(C)
+        assert s["n_fallback"] == cnt[0] and s["n_multi"] == cnt[1]
+        assert s["n_cfl"] == cnt[2] and s["n_merged"] == cnt[3]
+        assert s["n_interfacial"] == O.count_interfacial(st2)
+        assert s["n_ambiguous"] == int(amb.sum())
+
+
+def test_translation_run_parity_and_exact_shift():
+    """Config: 32^3, sphere r=0.15 at 0.35, u=(1,1,1), CFL 0.5, 20 steps."""
+    n = 32
+    sh = I.sphere_shape(n)
+    U = I.uniform_velocity(n)
+    Ud = [T(u) for u in U]
+    for exact in (False, True):
+        st = O.init(sh, exact=exact)
+        e = gpu_init(sh, exact)
+        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        e.front2vof(C)
+        C0 = C.cpu().numpy().copy()
+        V0 = e.stats(C)["volume"]
+        for k in range(20):
+            e.step(Ud, 1.0, 0.5 / n)
+            st, _ = O.step(st, U, 1.0, 0.5 / n)
+            compare_state(e, st, TOL, f"exact={exact} step {k}")
+            e.front2vof(C)
+        Co, _ = O.f2v(st)
+        compare_C(C, Co)
+        s = e.stats(C)
+        vo = O.volume(Co)
+        assert abs((s["volume"] + s["volume_comp"]) - (vo[0] + vo[1])) <= 1e-12 * abs(vo[0])
+        if exact:
+            assert np.max(np.abs(C.cpu().numpy() - np.roll(C0, (10, 10, 10), axis=(0, 1, 2)))) < 1e-12
+            assert abs(s["volume"] - V0) < 1e-10
+
+
+@pytest.mark.parametrize("n,steps,every", [(32, 192, 16), (64, 96, 24)])
+def test_deformation_run_parity(n, steps, every):
+    """LeVeque deformation (sec. 3.2), CFL 0.5: state compared at intervals,
+    bit-exact colours / existence, positions and C within 1e-12."""
+    sh = I.sphere_shape(n)
+    U = I.deformation_velocity(n)
+    Ud = [T(u) for u in U]
+    dt = 0.5 / n
+    st = O.init(sh)
+    e = gpu_init(sh)
+    C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    for k in range(steps):
+        g = I.deformation_time_factor(k * dt, 3.0)
+        e.step(Ud, g, dt)
+        st, _ = O.step(st, U, g, dt)
+        e.front2vof(C)
+        if (k + 1) % every == 0:
+            compare_state(e, st, TOL, f"n {n} step {k}")
+            Co, _ = O.f2v(st)
+            compare_C(C, Co, TOL, f"n {n} step {k}")
+
+
+def test_deformation_128_parity():
+    """Config: 128^3 deformation, CFL 0.5 -- first 48 steps compared every 8."""
+    test_deformation_run_parity(128, 48, 8)
+
+
+@pytest.mark.parametrize("R", [0.15, 0.42])
+def test_band_equals_full_grid(R):
+    """The band result equals processing every cell, also for a sphere whose
+    interior lies far outside the band."""
+    n = 64
+    sh = I.sphere_shape(n, centre=(0.5, 0.5, 0.5) if R > 0.3 else (0.35, 0.35, 0.35), R=R)
+    U = I.deformation_velocity(n)
+    Ud = [T(u) for u in U]
+    a, b = gpu_init(sh), gpu_init(sh)
+    b.set_option(E.EBIT_OPT_FULL_GRID, 1)
+    Ca = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    Cb = torch.zeros_like(Ca)
+    for k in range(60):
+        g = I.deformation_time_factor(k * 0.5 / n, 3.0)
+        a.step(Ud, g, 0.5 / n)
+        b.step(Ud, g, 0.5 / n)
+        a.front2vof(Ca)
+        b.front2vof(Cb)
+    torch.cuda.synchronize()
+    fa, sa = a.state()
+    fb, sb = b.state()
+    assert torch.equal(fa, fb)
+    for k in range(3):
+        assert torch.equal(sa[k], sb[k])
+    assert torch.equal(Ca, Cb)
+    assert a.stats(Ca)["n_active_cells"] < b.stats(Cb)["n_active_cells"]
+
+
+def test_deterministic_and_checkpoint_resume():
+    n = 32
+    sh = I.random_shape(n, 5)
+    U = I.fourier_velocity(n, seed=9, modes=4)
+    Ud = [T(u) for u in U]
+    runs = []
+    for _ in range(2):
+        e = gpu_init(sh, exact=True)
+        for k in range(6):
+            e.step(Ud, 1.0, 0.8 / n)
+        fl, s = e.state()
+        runs.append((fl.clone(), [x.clone() for x in s]))
+    assert torch.equal(runs[0][0], runs[1][0])
+    for k in range(3):
+        assert torch.equal(runs[0][1][k], runs[1][1][k])
+    # 3 steps, checkpoint, fresh context, 3 more steps == 6 steps
+    e = gpu_init(sh, exact=True)
+    for k in range(3):
+        e.step(Ud, 1.0, 0.8 / n)
+    fl, s = e.state()
+    ck = (fl.clone().cpu(), [x.clone().cpu() for x in s])
+    f2 = E.Ebit(n, "fp64", dev())
+    f2.load_state(ck[0].to(dev()), [x.to(dev()) for x in ck[1]])
+    for k in range(3):
+        f2.step(Ud, 1.0, 0.8 / n)
+    fl2, s2 = f2.state()
+    assert torch.equal(fl2, runs[0][0])
+    for k in range(3):
+        assert torch.equal(s2[k], runs[0][1][k])
+
+
+def test_minimal_grid_and_empty_state():
+    n = 8
+    e = gpu_from_oracle(O.init(I.random_shape(n, 2), exact=True))
+    st = O.init(I.random_shape(n, 2), exact=True)
+    U = I.fourier_velocity(n, seed=1, modes=2)
+    for d in range(3):
+        e.sweep(d, T(U[d]), 1.0, 1.0 / n)
+        st, _ = O.sweep(st, d, 1.0, 1.0 / n, U[d])
+    compare_state(e, st, TOL, "n=8")
+    # no interface at all: nothing moves, C = colour everywhere
+    n = 16
+    phi = -np.ones((n, n, n))
+    sh = I.Shape(n, phi, [phi, phi, phi], [np.zeros((n, n, n))] * 3)
+    e = gpu_init(sh)
+    e.step([T(np.ones((n, n, n)))] * 3, 1.0, 0.5 / n)
+    C = torch.ones((n, n, n), dtype=torch.float64, device=dev())
+    e.front2vof(C)
+    s = e.stats(C)
+    assert s["volume"] == 0.0 and s["n_interfacial"] == 0 and sum(s["n_markers"]) == 0
+
+
+def test_courant_violation_is_reported():
+    n = 16
+    e = gpu_init(I.sphere_shape(n, centre=(0.5, 0.5, 0.5), R=0.3))
+    e.sweep(0, T(np.full((n, n, n), 1.5)), 1.0, 1.0 / n)
+    C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    e.front2vof(C)
+    with pytest.raises(E.EbitError) as ex:
+        e.stats(C)
+    assert ex.value.code == E.EBIT_ECFL
