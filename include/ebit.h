@@ -127,8 +127,9 @@ typedef struct {
     int64_t n_multi;        /* sweeps so far: new unaligned markers with > 1 crossing */
     int64_t n_cfl;          /* sweeps so far: markers moved by more than one cell */
     int64_t n_merged;       /* sweeps so far: aligned edges reached by > 1 marker */
-    int64_t n_active_cells; /* cells processed by the last sweep (work-list size) */
+    int64_t n_active_cells; /* sweeps so far: cells processed (work-list sizes) */
     int64_t step_sweeps;    /* sweeps so far */
+    int64_t n_interfacial_sum; /* sum of n_interfacial over every ebit_front2vof so far */
 } ebit_stats_t;
 
 /*

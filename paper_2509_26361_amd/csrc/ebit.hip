@@ -29,7 +29,7 @@ constexpr int kRedBlocks = 1024;
 
 enum {
     ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_INTERFACIAL, ST_AMBIG, ST_ACTIVE,
-    ST_MARK0, ST_MARK1, ST_MARK2, ST_SWEEPS, ST_COUNT = 16
+    ST_MARK0, ST_MARK1, ST_MARK2, ST_SWEEPS, ST_INTER_SUM, ST_COUNT = 16
 };
 
 // device work space carved out of the caller's scratch buffer
@@ -643,6 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_f2v(F2VArgs<T> a)
         a.C[qc[0]] = C;
         if (__ballot(inter)) {
             wave_add(&a.w.stat[ST_INTERFACIAL], inter);
+            wave_add(&a.w.stat[ST_INTER_SUM], inter);
             wave_add(&a.w.stat[ST_AMBIG], amb);
         }
     }
@@ -961,6 +962,7 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     out->n_merged = (int64_t)stat[ST_MERGED];
     out->n_active_cells = (int64_t)stat[ST_ACTIVE];
     out->step_sweeps = (int64_t)stat[ST_SWEEPS];
+    out->n_interfacial_sum = (int64_t)stat[ST_INTER_SUM];
     return out->n_cfl ? EBIT_ECFL : EBIT_OK;
 }
 

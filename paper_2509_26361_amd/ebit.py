@@ -51,6 +51,7 @@ class Stats(ctypes.Structure):
         ("n_merged", ctypes.c_int64),
         ("n_active_cells", ctypes.c_int64),
         ("step_sweeps", ctypes.c_int64),
+        ("n_interfacial_sum", ctypes.c_int64),
     ]
 
     def as_dict(self):
