@@ -155,6 +155,7 @@ def main():
                               "mean": n_start / K},
         "volume": {"start": st0["volume"] + st0["volume_comp"], "end": st1["volume"] + st1["volume_comp"]},
         "counters": {k: st1[k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged")},
+        "band_bricks_per_sweep": (st1["n_active_cells"] - st0["n_active_cells"]) / 64.0 / (3 * K),
     }
 
     if not a.no_cpu_baseline:

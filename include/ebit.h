@@ -121,7 +121,8 @@ typedef struct {
     double volume;          /* sum of C over all cells (compensated, FP64) */
     double volume_comp;     /* its compensation term: volume + volume_comp */
     int64_t n_interfacial;  /* cells with a marker on any of their 12 edges, at the last ebit_front2vof */
-    int64_t n_ambiguous;    /* of those: a face with 4 markers or more than one loop */
+    int64_t n_ambiguous;    /* cells recomputed by the last ebit_front2vof (all cells for a new C) with a
+                               4-marker face or more than one loop */
     int64_t n_markers[3];   /* markers per edge family in the current state */
     int64_t n_fallback;     /* sweeps so far: edges placed by the no-crossing fallback */
     int64_t n_multi;        /* sweeps so far: new unaligned markers with > 1 crossing */

@@ -3,12 +3,29 @@
 // advection sweep and Front2VOF (Pan et al., arXiv 2509.26361, secs. 2.1-2.5,
 // 3.1), plus a deterministic compensated volume reduction.
 //
-// Work is restricted to a band of 4x4x4-node bricks around the interface: a
-// brick is processed when it or one of its 26 neighbours held a marker before
-// the current or the previous sweep (markers move at most one cell per sweep
-// and every output depends only on markers within three cells).  Outside the
-// band the state is constant, so the result equals a full-grid sweep.  One
-// wavefront handles one brick (64 nodes, one lane per node).
+// Band.  Work is restricted to 4x4x4-node bricks near the interface.  A sweep
+// processes a brick when it is, or neighbours (26-neighbourhood), a brick that
+// held a marker before this sweep or before the previous one: markers move at
+// most one cell per sweep and every output depends only on markers within
+// three cells, so outside the band the state is constant and the result
+// equals a full-grid sweep.  Activity is kept as per-brick stamps (the sweep
+// number at which a brick entered the band), so no list and no shared counter
+// is needed: each sweep stamps the bricks of the next one.
+//
+// Chunks.  Bricks are grouped in chunks of 64 (brick c + k * nchunks, k <
+// 64), scattered over the grid.  A workgroup owns a chunk while processing
+// it: it writes the chunk's task segments, task counts and counters with
+// plain stores, so the hot kernels issue no same-address atomics (those are
+// serialised at memory across the XCDs of the chip).
+//
+// Sweep = two kernels.  Phase A (one 64-lane workgroup per chunk, one lane per
+// node of the current brick, the brick and a one-node halo staged in LDS):
+// new node colours, aligned markers, which edges carry a marker afterwards,
+// colours of faces with uniform corners, and the task segments -- the nodes
+// whose new unaligned marker must be placed by the circle fit and the faces
+// whose corners differ.  Phase B (256-lane blocks over chunks): the tasks,
+// one per lane, densely.  Front2VOF is split the same way: full/empty cells
+// first, then one interfacial cell per lane.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -23,69 +40,102 @@ using namespace ebit;
 
 namespace {
 
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kRedBlocks = 1024;
+constexpr int kChunk = 64;              // bricks per chunk
+constexpr int kSeg = kChunk * 64;       // task segment length per chunk (one per node)
 
+// totals reduced from the per-chunk counters
 enum {
-    ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_INTERFACIAL, ST_AMBIG, ST_ACTIVE,
-    ST_MARK0, ST_MARK1, ST_MARK2, ST_SWEEPS, ST_INTER_SUM, ST_COUNT = 16
+    ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB,
+    ST_MARK0, ST_MARK1, ST_MARK2, ST_COUNT = 16
 };
-
-// device work space carved out of the caller's scratch buffer
-struct Work {
-    uint8_t *bmark;      // brick holds a marker (after the last sweep that processed it)
-    uint8_t *coreprev;   // brick was in the dilated marker set before the previous sweep
-    uint8_t *touched;    // brick written since the last Front2VOF
-    int32_t *list;       // active bricks
-    uint32_t *cnt;       // [2] list lengths, used alternately
-    unsigned long long *stat;   // ST_*
-    double *part;        // 2 * kRedBlocks reduction partials
-};
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-size_t work_layout(int n, Work *w, char *base)
-{
-    size_t nb = (size_t)(n / 4) * (n / 4) * (n / 4);
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return base ? base + o : nullptr; };
-    char *p;
-    p = take(nb); if (w) w->bmark = (uint8_t *)p;
-    p = take(nb); if (w) w->coreprev = (uint8_t *)p;
-    p = take(nb); if (w) w->touched = (uint8_t *)p;
-    p = take(nb * 4); if (w) w->list = (int32_t *)p;
-    p = take(2 * sizeof(uint32_t)); if (w) w->cnt = (uint32_t *)p;
-    p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
-    p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
-    return off;
-}
+// per-chunk counters: cumulative over sweeps / Front2VOF calls, except the
+// last-Front2VOF ones
+enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_SUM, CS_INTER, CS_AMB, CS_COUNT };
 
 struct Geo {
     int n;
     int nb1;        // bricks per axis
     long nn;        // n*n
+    int nb;         // bricks
+    int nc;         // chunks
+    long hmul;      // brick of chunk slot j: (j * hmul) mod nb, hmul coprime with nb
 };
 
-__device__ __forceinline__ void brick_node(const Geo &g, int b, int lane, int &x, int &y, int &z)
+// Chunk ch holds slots 64 ch .. 64 ch + 63; slot j is brick (j * hmul) mod nb,
+// a permutation that scatters a chunk's bricks over the grid (balanced work
+// per chunk, no same-address contention between chunks).
+__device__ __forceinline__ int chunk_brick(const Geo &g, int ch, int k, bool &valid)
 {
-    int bx = b % g.nb1, by = (b / g.nb1) % g.nb1, bz = b / (g.nb1 * g.nb1);
-    x = bx * 4 + (lane & 3);
-    y = by * 4 + ((lane >> 2) & 3);
-    z = bz * 4 + (lane >> 4);
+    long j = (long)ch * 64 + k;
+    valid = j < g.nb;
+    return valid ? (int)((j * g.hmul) % g.nb) : 0;
 }
 
-__device__ __forceinline__ void wave_add(unsigned long long *dst, int v)
+// device work space carved out of the caller's scratch buffer
+struct Work {
+    uint32_t *cm[3];     // cm[t % 3][b] == t <=> brick b is next to a marker-holding brick before sweep t
+    uint32_t *fmark;     // fmark[b] == g <=> brick b must be revisited by Front2VOF generation g
+    uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
+    uint32_t *task[4];   // per chunk kSeg node indices: unaligned fit (plane 1, 2), face colour (plane 1, 2)
+    uint32_t *tcnt;      // [4][nc] task counts
+    uint32_t *ctask;     // per chunk kSeg interfacial cells
+    uint32_t *ccnt;      // [nc]
+    unsigned long long *cs;     // [CS_COUNT][nc] per-chunk counters
+    unsigned long long *stat;   // ST_* totals
+    double *part;        // 2 * kRedBlocks reduction partials
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int chunks_for(int n)
 {
-    // sum a per-lane count over the wave, one atomic per wave
-    unsigned long long bal;
-    int tot = 0;
+    long nb = (long)(n / 4) * (n / 4) * (n / 4);
+    return (int)((nb + kChunk - 1) / kChunk);
+}
+
+size_t work_layout(int n, Work *w, char *base)
+{
+    size_t nb = (size_t)(n / 4) * (n / 4) * (n / 4);
+    size_t nc = (size_t)chunks_for(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return base ? base + o : nullptr; };
+    char *p;
+    for (int k = 0; k < 3; ++k) { p = take(nb * 4); if (w) w->cm[k] = (uint32_t *)p; }
+    p = take(nb * 4); if (w) w->fmark = (uint32_t *)p;
+    p = take(nb * 4); if (w) w->bcnt = (uint32_t *)p;
+    for (int k = 0; k < 4; ++k) { p = take(nc * kSeg * 4); if (w) w->task[k] = (uint32_t *)p; }
+    p = take(4 * nc * 4); if (w) w->tcnt = (uint32_t *)p;
+    p = take(nc * kSeg * 4); if (w) w->ctask = (uint32_t *)p;
+    p = take(nc * 4); if (w) w->ccnt = (uint32_t *)p;
+    p = take(CS_COUNT * nc * 8); if (w) w->cs = (unsigned long long *)p;
+    p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
+    p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
+    return off;
+}
+
+__device__ __forceinline__ int brick_shift(int b, int nb1, int dx, int dy, int dz)
+{
+    int bx = b % nb1, by = (b / nb1) % nb1, bz = b / (nb1 * nb1);
+    return wrp(bx + dx, nb1) + nb1 * (wrp(by + dy, nb1) + nb1 * wrp(bz + dz, nb1));
+}
+
+// sum of a per-lane value over the wave (result valid in every lane)
+__device__ __forceinline__ int wave_sum(int v)
+{
 #pragma unroll
-    for (int bit = 0; bit < 4; ++bit) {
-        bal = __ballot((v >> bit) & 1);
-        tot += __popcll(bal) << bit;
-    }
-    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(dst, (unsigned long long)tot);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Wave-aggregated write of the lanes' entries at seg[pos...]; `pos` is the
+// wave-uniform fill level.
+__device__ __forceinline__ void wave_put(uint32_t *seg, int &pos, bool take, uint32_t val)
+{
+    unsigned long long bal = __ballot(take);
+    int lane = threadIdx.x & 63;
+    if (take) seg[pos + __popcll(bal & ((1ull << lane) - 1ull))] = val;
+    pos += __popcll(bal);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,103 +191,42 @@ __global__ __launch_bounds__(256) void k_init(Geo g, const double *__restrict__ 
     fl[q] = out;
 }
 
-// brick marks of a freshly initialised (or caller-filled) state; every brick
-// is marked touched so the first Front2VOF covers the whole grid
-__global__ __launch_bounds__(kBlock) void k_mark_all(Geo g, const uint8_t *__restrict__ fl, Work w, int nbricks)
+// Stamps of a freshly initialised (or caller-filled) state: the first sweep
+// (t = 2; stamps start at 0) processes the bricks next to a brick holding a
+// marker.
+__global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restrict__ fl, Work w)
 {
-    int b = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (b >= nbricks) return;
-    int x, y, z;
-    brick_node(g, b, lane, x, y, z);
-    long q = x + (long)g.n * y + g.nn * z;
-    unsigned long long bal = __ballot((fl[q] & 0x70) != 0);
-    if (lane == 0) {
-        w.bmark[b] = bal != 0;
-        w.coreprev[b] = 0;
-        w.touched[b] = 1;
+    const int lane = threadIdx.x;
+    for (int b = blockIdx.x; b < g.nb; b += gridDim.x) {
+        int bx = b % g.nb1, by = (b / g.nb1) % g.nb1, bz = b / (g.nb1 * g.nb1);
+        int x = bx * 4 + (lane & 3), y = by * 4 + ((lane >> 2) & 3), z = bz * 4 + (lane >> 4);
+        long q = x + (long)g.n * y + g.nn * z;
+        bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
+        if (hasm && lane < 27) w.cm[2][brick_shift(b, g.nb1, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1)] = 2u;
     }
-    if (b == 0 && lane == 0) {
-        w.cnt[0] = 0;
-        w.cnt[1] = 0;
-#pragma unroll
-        for (int t = 0; t < ST_COUNT; ++t) w.stat[t] = 0;
+}
+
+// zero the stamps and counters
+__global__ void k_zero_work(Work w, Geo g)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.nb) {
+        w.cm[0][i] = 0;
+        w.cm[1][i] = 0;
+        w.cm[2][i] = 0;
+        w.fmark[i] = 0;
+        w.bcnt[i] = 0;
     }
+    if (i < g.nc) {
+        for (int k = 0; k < 4; ++k) w.tcnt[k * g.nc + i] = 0;
+        w.ccnt[i] = 0;
+        for (int k = 0; k < CS_COUNT; ++k) w.cs[k * g.nc + i] = 0;
+    }
+    if (i < ST_COUNT) w.stat[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// a1: band compaction
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ bool dilated(const Geo &g, const uint8_t *__restrict__ m, int b)
-{
-    int nb = g.nb1;
-    int bx = b % nb, by = (b / nb) % nb, bz = b / (nb * nb);
-    bool any = false;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx)
-                any |= m[wrp(bx + dx, nb) + nb * (wrp(by + dy, nb) + nb * wrp(bz + dz, nb))] != 0;
-    return any;
-}
-
-// Sweep work list: bricks in the dilated marker set now or before the
-// previous sweep (full = every brick).  Appends to list, counter cnt[slot].
-__global__ __launch_bounds__(256) void k_band_sweep(Geo g, Work w, int nbricks, int slot, int full)
-{
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = false;
-    if (b < nbricks) {
-        bool core = dilated(g, w.bmark, b);
-        act = full || core || w.coreprev[b];
-        w.coreprev[b] = core;
-        if (act) w.touched[b] = 1;
-    }
-    // wave-aggregated append
-    unsigned long long bal = __ballot(act);
-    int lane = threadIdx.x & 63;
-    uint32_t basei = 0;
-    if (lane == 0 && bal) basei = atomicAdd(&w.cnt[slot], (uint32_t)__popcll(bal));
-    basei = __shfl(basei, 0);
-    if (act) {
-        unsigned long long below = bal & ((1ull << lane) - 1ull);
-        uint32_t at = basei + (uint32_t)__popcll(below);
-        if (at < (uint32_t)nbricks) w.list[at] = b;
-    }
-}
-
-// Front2VOF work list: bricks touched since the last Front2VOF, dilated
-// (a cell reads edges of its +x/+y/+z neighbours).  Clears touched after a
-// grid-wide pass: done by the Front2VOF kernel itself.
-__global__ __launch_bounds__(256) void k_band_f2v(Geo g, Work w, int nbricks, int slot, int full)
-{
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = false;
-    if (b < nbricks) act = full || dilated(g, w.touched, b);
-    unsigned long long bal = __ballot(act);
-    int lane = threadIdx.x & 63;
-    uint32_t basei = 0;
-    if (lane == 0 && bal) basei = atomicAdd(&w.cnt[slot], (uint32_t)__popcll(bal));
-    basei = __shfl(basei, 0);
-    if (act) {
-        unsigned long long below = bal & ((1ull << lane) - 1ull);
-        uint32_t at = basei + (uint32_t)__popcll(below);
-        if (at < (uint32_t)nbricks) w.list[at] = b;
-    }
-    if (b == 0) {
-        w.stat[ST_INTERFACIAL] = 0;
-        w.stat[ST_AMBIG] = 0;
-    }
-}
-
-__global__ void k_clear_touched(Work w, int nbricks)
-{
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nbricks) w.touched[b] = 0;
-}
-
-// ---------------------------------------------------------------------------
-// a2-a4: one sweep along axis D (secs. 2.1-2.4)
+// a1-a4: one sweep along axis D (secs. 2.1-2.4)
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -248,127 +237,306 @@ struct SweepArgs {
     uint8_t *flo;
     T *so[3];
     const T *U;
-    T c;
+    T c;              // (dt n) g
     Work w;
-    int slot;
+    uint32_t t;       // sweep sequence number (>= 2)
+    uint32_t fgen;    // generation of the next Front2VOF
+    int full;         // process every brick
 };
 
+// Phase A tile: flags and advected coordinate of the D-edge markers of the
+// brick's nodes and their neighbours at offsets -1..+1 along D and +1 across,
+// indexed iD + kAD (i1 + kAA i2), (iD, i1, i2) = offsets (+1, 0, 0) along (D, A1, A2).
+constexpr int kAD = 6, kAA = 5, kATile = kAD * kAA * kAA;
+
+// Phase A of a sweep, one 64-lane workgroup per chunk, its active bricks one
+// after the other: new node colours (one flip per aligned marker crossing a
+// node, Fig. 4), the aligned markers (land on the edge they reach, pairs
+// annihilate, Fig. 5a), which edges carry a marker afterwards (one marker iff
+// the end colours differ, sec. 2.2), the colour of faces with uniform
+// corners, and the chunk's task segments for phase B.  Stamps the bricks of
+// the next sweep and those Front2VOF must revisit.
 template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> a)
+__global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * kWavesPerBlock;
-    const int nbr = a.g.nb1 * a.g.nb1 * a.g.nb1;
-    const int count = min((int)a.w.cnt[a.slot], nbr);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.w.cnt[a.slot ^ 1] = 0;              // for the next compaction
-        atomicAdd(&a.w.stat[ST_ACTIVE], (unsigned long long)count * 64ull);
-        atomicAdd(&a.w.stat[ST_SWEEPS], 1ull);
+    __shared__ uint8_t tfl[kATile];
+    __shared__ double txd[kATile];
+    const int lane = threadIdx.x;
+    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb, nc = a.g.nc;
+    const uint32_t t = a.t;
+    const uint32_t *cm_cur = a.w.cm[t % 3], *cm_prev = a.w.cm[(t + 2) % 3];
+    uint32_t *cm_next = a.w.cm[(t + 1) % 3];
+    const long str[3] = {1, (long)n, a.g.nn};
+    const int lu[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int tself = (lu[D] + 1) + kAD * (lu[A1] + kAA * lu[A2]);
+    int ext[3], lo[3];
+    ext[D] = kAD; ext[A1] = kAA; ext[A2] = kAA;
+    lo[D] = -1; lo[A1] = 0; lo[A2] = 0;
+
+    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+        bool valid;
+        const int bl = chunk_brick(a.g, ch, lane, valid);
+        const bool act = valid && (a.full || cm_cur[bl] == t || cm_prev[bl] == t - 1);
+        unsigned long long pending = __ballot(act);
+        int nt[4] = {0, 0, 0, 0};
+        int fbc = 0, cflc = 0, mergedc = 0;
+        const int nact = __popcll(pending);
+        while (pending) {
+            const int k = __ffsll((long long)pending) - 1;
+            pending &= pending - 1;
+            const int b = __shfl(bl, k);
+            const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+            int cfl = 0;
+            // stage flags and the Euler step (eq. Eq_marker_dis) of D-edge markers;
+            // all flag loads first, then all marker loads
+            constexpr int kR = (kATile + 63) / 64;
+            long qr[kR];
+            uint8_t fr[kR];
+            int gpd[kR];
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                int kk = lane + 64 * r;
+                int kc = kk < kATile ? kk : kATile - 1;
+                int kt[3] = {kc % ext[0], (kc / ext[0]) % ext[1], kc / (ext[0] * ext[1])};
+                int gp[3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) gp[e] = wrp(org[e] + lo[e] + kt[e], n);
+                qr[r] = gp[0] + str[1] * gp[1] + str[2] * gp[2];
+                gpd[r] = gp[D];
+                fr[r] = a.fl[qr[r]];
+            }
+            T sD[kR], U0[kR], UD[kR];
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                sD[r] = U0[r] = UD[r] = T(0);
+                if ((fr[r] >> (4 + D)) & 1) {
+                    const long q = qr[r];
+                    sD[r] = a.s[D][q];
+                    U0[r] = a.U[q];
+                    UD[r] = a.U[gpd[r] + 1 == n ? q - (long)(n - 1) * str[D] : q + str[D]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                int kk = lane + 64 * r;
+                if (kk >= kATile) continue;
+                int kt[3] = {kk % ext[0], (kk / ext[0]) % ext[1], kk / (ext[0] * ext[1])};
+                int ti = kt[D] + kAD * (kt[A1] + kAA * kt[A2]);
+                double xd = 0.0;
+                if ((fr[r] >> (4 + D)) & 1) {
+                    T u = U0[r] + sD[r] * (UD[r] - U0[r]);
+                    T del = a.c * u;
+                    xd = (double)sD[r] + (double)del;
+                    const bool own = kt[D] >= 1 && kt[D] < 5 && kt[A1] < 4 && kt[A2] < 4;
+                    if (own && fabs((double)del) > 1.0) ++cfl;
+                }
+                tfl[ti] = fr[r];
+                txd[ti] = xd;
+            }
+            __syncthreads();
+            // new colours of the tile nodes whose D-predecessor is in the tile
+            for (int kk = lane; kk < kATile; kk += 64) {
+                if (kk % kAD == 0) continue;
+                uint8_t f = tfl[kk], fm = tfl[kk - 1];
+                int c = f & 1;
+                if (((fm >> (4 + D)) & 1) && txd[kk - 1] >= 1.0) c ^= 1;
+                if (((f >> (4 + D)) & 1) && txd[kk] < 0.0) c ^= 1;
+                tfl[kk] = (uint8_t)((f & 0x7f) | (c << 7));
+            }
+            __syncthreads();
+            auto ncol = [&](int di, int d1, int d2) { return (tfl[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
+            const uint8_t fself = tfl[tself];
+            const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
+            const int c00 = ncol(0, 0, 0), c10 = ncol(1, 0, 0);
+            uint8_t out = (uint8_t)c00;
+            T sdn = T(0);
+            int fb = 0, merged = 0;
+            {
+                uint8_t fm = tfl[tself - 1], fp = tfl[tself + 1];
+                bool hm = (fm >> (4 + D)) & 1, h0 = (fself >> (4 + D)) & 1, hp = (fp >> (4 + D)) & 1;
+                double xm = txd[tself - 1], x0 = txd[tself], xp = txd[tself + 1];
+                bool lm = hm && xm >= 1.0, l0 = h0 && x0 >= 0.0 && x0 < 1.0, lp = hp && xp < 0.0;
+                int kl = (int)lm + (int)l0 + (int)lp;
+                if (c00 != c10) {
+                    double v;
+                    if (kl == 1) v = lm ? xm - 1.0 : (l0 ? x0 : xp + 1.0);
+                    else if (kl == 3) {
+                        double v0 = xm - 1.0, v1 = x0, v2 = xp + 1.0;
+                        double lo2 = v0 < v1 ? v0 : v1, hi = v0 < v1 ? v1 : v0;
+                        v = v2 < lo2 ? lo2 : (v2 > hi ? hi : v2);
+                        merged += 1;
+                    } else {
+                        v = 0.5;
+                        fb += 1;
+                    }
+                    sdn = clamp_frac<T>((T)v);
+                    out |= (uint8_t)(1u << (4 + D));
+                } else if (kl >= 2) {
+                    merged += 1;
+                }
+            }
+            out |= (uint8_t)(fself & (1u << (1 + D)));   // faces normal to D keep their colour
+            // Courant check of the unaligned markers stored at this node
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int A = e == 0 ? A1 : A2;
+                if ((fself >> (4 + A)) & 1) {
+                    long q1 = org[A] + lu[A] + 1 == n ? qs - (long)(n - 1) * str[A] : qs + str[A];
+                    T s = a.s[A][qs];
+                    T U0s = a.U[qs];
+                    T del = a.c * (U0s + s * (a.U[q1] - U0s));
+                    if (fabs((double)del) > 1.0) ++cfl;
+                }
+            }
+            bool task[4];
+            {
+                const int c01 = ncol(0, 1, 0), c11 = ncol(1, 1, 0);   // plane (D, A1)
+                task[0] = c00 != c01;
+                task[2] = !(c00 == c10 && c00 == c01 && c00 == c11);
+                if (task[0]) out |= (uint8_t)(1u << (4 + A1));
+                if (!task[2]) out |= (uint8_t)(c00 << (1 + A2));
+            }
+            {
+                const int c01 = ncol(0, 0, 1), c11 = ncol(1, 0, 1);   // plane (D, A2)
+                task[1] = c00 != c01;
+                task[3] = !(c00 == c10 && c00 == c01 && c00 == c11);
+                if (task[1]) out |= (uint8_t)(1u << (4 + A2));
+                if (!task[3]) out |= (uint8_t)(c00 << (1 + A1));
+            }
+            a.flo[qs] = out;
+            a.so[D][qs] = sdn;
+            if (!task[0]) a.so[A1][qs] = T(0);
+            if (!task[1]) a.so[A2][qs] = T(0);
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) wave_put(a.w.task[kt] + (size_t)ch * kSeg, nt[kt], task[kt], (uint32_t)qs);
+
+            // stamps: the next sweep takes the bricks next to a brick holding
+            // markers now (and this sweep's core); Front2VOF revisits the cells
+            // of bricks that hold markers or whose colours / markers changed (a
+            // cell also reads the edges stored at its upper neighbours)
+            const bool hasm = __ballot((out & 0x70) != 0) != 0;
+            const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
+            if (hasm && lane < 27) cm_next[brick_shift(b, nb1, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1)] = t + 1;
+            if ((hasm || chg) && lane >= 32 && lane < 40) {
+                int d = lane - 32;
+                a.w.fmark[brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2))] = a.fgen;
+            }
+            fbc += fb;
+            cflc += cfl;
+            mergedc += merged;
+            __syncthreads();   // the tile is reused by the next brick
+        }
+        // the chunk's task counts and counters (this workgroup owns the chunk)
+        fbc = wave_sum(fbc);
+        cflc = wave_sum(cflc);
+        mergedc = wave_sum(mergedc);
+        if (lane < 4) {
+            const int v = lane == 0 ? nt[0] : (lane == 1 ? nt[1] : (lane == 2 ? nt[2] : nt[3]));
+            a.w.tcnt[lane * nc + ch] = (uint32_t)v;
+        }
+        if (lane == 0) {
+            a.w.cs[CS_FALLBACK * nc + ch] += (unsigned long long)fbc;
+            a.w.cs[CS_CFL * nc + ch] += (unsigned long long)cflc;
+            a.w.cs[CS_MERGED * nc + ch] += (unsigned long long)mergedc;
+            a.w.cs[CS_ACTIVE * nc + ch] += (unsigned long long)nact * 64ull;
+        }
     }
+}
+
+// Old-state accessor for phase B: global memory, periodic, offsets relative
+// to the task's node in the plane (D, A).
+template <typename T, int D, int A>
+struct GlobAcc {
+    static constexpr int B = 3 - D - A;
+    const uint8_t *__restrict__ fl;
+    const T *__restrict__ sD;
+    const T *__restrict__ sA;
+    const T *__restrict__ U;
+    T c;
+    int n;
+    int ci, cj;
+    long base, strD, strA;
+    __device__ __forceinline__ long node(int i, int j) const
+    {
+        return (long)wrp(ci + i, n) * strD + (long)wrp(cj + j, n) * strA + base;
+    }
+    __device__ __forceinline__ uint8_t f(int i, int j) const { return fl[node(i, j)]; }
+    __device__ __forceinline__ double xd(int i, int j) const
+    {
+        long q = node(i, j);
+        T s = sD[q];
+        T U0 = U[q];
+        T u = U0 + s * (U[node(i + 1, j)] - U0);
+        T del = c * u;
+        return (double)s + (double)del;
+    }
+    __device__ __forceinline__ double dva(int i, int j) const
+    {
+        long q = node(i, j);
+        T s = sA[q];
+        T U0 = U[q];
+        T u = U0 + s * (U[node(i, j + 1)] - U0);
+        return (double)(c * u);
+    }
+    __device__ __forceinline__ T sa(int i, int j) const { return sA[node(i, j)]; }
+};
+
+template <typename T, int D, int A>
+__device__ __forceinline__ PlaneAlg<T, D, A, GlobAcc<T, D, A>> plane_at(const SweepArgs<T> &a, long q)
+{
+    constexpr int B = 3 - D - A;
     const int n = a.g.n;
     const long str[3] = {1, (long)n, a.g.nn};
-    for (int t = wave; t < count; t += nwaves) {
-        const int b = a.w.list[t];
-        if ((unsigned)b >= (unsigned)nbr) continue;
-        int P[3];
-        brick_node(a.g, b, lane, P[0], P[1], P[2]);
-        const long q = P[0] + str[1] * P[1] + str[2] * P[2];
+    int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / a.g.nn)};
+    GlobAcc<T, D, A> g;
+    g.fl = a.fl; g.sD = a.s[D]; g.sA = a.s[A]; g.U = a.U; g.c = a.c; g.n = n;
+    g.ci = P[D]; g.cj = P[A]; g.base = (long)P[B] * str[B]; g.strD = str[D]; g.strA = str[A];
+    return PlaneAlg<T, D, A, GlobAcc<T, D, A>>{g};
+}
 
-        Plane<T, D, A1> p1;   // faces with normal A2
-        p1.fl = a.fl; p1.sD = a.s[D]; p1.sA = a.s[A1]; p1.U = a.U; p1.c = a.c; p1.n = n;
-        p1.ci = P[D]; p1.cj = P[A1]; p1.base = (long)P[A2] * str[A2]; p1.strD = str[D]; p1.strA = str[A1];
-        Plane<T, D, A2> p2;   // faces with normal A1
-        p2.fl = a.fl; p2.sD = a.s[D]; p2.sA = a.s[A2]; p2.U = a.U; p2.c = a.c; p2.n = n;
-        p2.ci = P[D]; p2.cj = P[A2]; p2.base = (long)P[A1] * str[A1]; p2.strD = str[D]; p2.strA = str[A2];
-
-        const uint8_t f0 = a.fl[q];
-        int fb = 0, multi = 0, cfl = 0, merged = 0;
-
-        // Courant check of the markers stored at this node
-        {
-            auto chk = [&](int e, const T *se) {
-                if ((f0 >> (4 + e)) & 1) {
-                    long q1 = q + (P[e] + 1 == n ? -(long)(n - 1) * str[e] : str[e]);
-                    T s = se[q];
-                    T U0 = a.U[q], U1 = a.U[q1];
-                    T u = U0 + s * (U1 - U0);
-                    T del = a.c * u;
-                    if (fabs((double)del) > 1.0) cfl += 1;
+// Phase B: the chunks' task segments, one task per lane: circle-fit placement
+// of each new unaligned marker (sec. 2.1) and the colour of each face whose
+// corners differ (phase A wrote every other output).
+template <typename T, int D>
+__global__ __launch_bounds__(64) void k_sweep_b(SweepArgs<T> a)
+{
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    const int nc = a.g.nc;
+    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+        uint32_t c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = min(a.w.tcnt[k * nc + ch], (uint32_t)kSeg);
+        const uint32_t total = c[0] + c[1] + c[2] + c[3];
+        int fbt = 0, multit = 0;
+        for (uint32_t i = threadIdx.x; i < total; i += 64) {
+            uint32_t k = i;
+            int type = 0;
+            if (k >= c[0]) { k -= c[0]; type = 1;
+                if (k >= c[1]) { k -= c[1]; type = 2;
+                    if (k >= c[2]) { k -= c[2]; type = 3; } } }
+            const long q = (long)a.w.task[type][(size_t)ch * kSeg + k];
+            if (type == 0) {
+                a.so[A1][q] = plane_at<T, D, A1>(a, q).unaligned(fbt, multit);
+            } else if (type == 1) {
+                a.so[A2][q] = plane_at<T, D, A2>(a, q).unaligned(fbt, multit);
+            } else {
+                const int c00 = a.flo[q] & 1;
+                int fc = type == 2 ? plane_at<T, D, A1>(a, q).face_colour(c00)
+                                   : plane_at<T, D, A2>(a, q).face_colour(c00);
+                if (fc) {
+                    // faces of one node are written by two tasks: OR into the byte's word
+                    const int bit = type == 2 ? 1 + A2 : 1 + A1;
+                    unsigned int *w = (unsigned int *)(a.flo + (q & ~3L));
+                    atomicOr(w, (unsigned int)(1u << bit) << (8 * (int)(q & 3)));
                 }
-            };
-            chk(0, a.s[0]);
-            chk(1, a.s[1]);
-            chk(2, a.s[2]);
-        }
-
-        // aligned markers and node colours (Fig. 4; annihilation, Fig. 5a)
-        const int c00 = p1.newcol(0, 0);
-        const int c10 = p1.newcol(1, 0);
-        uint8_t out = (uint8_t)c00;
-        T sd_new = T(0);
-        {
-            bool hm = p1.hhas(-1, 0), h0 = p1.hhas(0, 0), hp = p1.hhas(1, 0);
-            double xm = hm ? p1.xd(-1, 0) : 0.0, x0 = h0 ? p1.xd(0, 0) : 0.0, xp = hp ? p1.xd(1, 0) : 0.0;
-            bool lm = hm && xm >= 1.0, l0 = h0 && x0 >= 0.0 && x0 < 1.0, lp = hp && xp < 0.0;
-            int k = (int)lm + (int)l0 + (int)lp;
-            if (c00 != c10) {
-                double v;
-                if (k == 1) v = lm ? xm - 1.0 : (l0 ? x0 : xp + 1.0);
-                else if (k == 3) {
-                    double v0 = xm - 1.0, v1 = x0, v2 = xp + 1.0;
-                    double lo = v0 < v1 ? v0 : v1, hi = v0 < v1 ? v1 : v0;
-                    v = v2 < lo ? lo : (v2 > hi ? hi : v2);
-                    merged += 1;
-                } else {
-                    v = 0.5;
-                    fb += 1;
-                }
-                sd_new = clamp_frac<T>((T)v);
-                out |= (uint8_t)(1u << (4 + D));
-            } else if (k >= 2) {
-                merged += 1;
             }
         }
-        out |= (uint8_t)(f0 & (1u << (1 + D)));   // faces normal to D keep their colour
-
-        // plane (D, A1): unaligned A1-edge and faces with normal A2
-        T sa1_new = T(0);
-        {
-            const int c01 = p1.newcol(0, 1);
-            if (c00 != c01) {
-                sa1_new = p1.unaligned(fb, multi);
-                out |= (uint8_t)(1u << (4 + A1));
-            }
-            const int c11 = p1.newcol(1, 1);
-            int fc = (c00 == c10 && c00 == c01 && c00 == c11) ? c00 : p1.face_colour(c00);
-            out |= (uint8_t)(fc << (1 + A2));
-        }
-        // plane (D, A2): unaligned A2-edge and faces with normal A1
-        T sa2_new = T(0);
-        {
-            const int c01 = p2.newcol(0, 1);
-            if (c00 != c01) {
-                sa2_new = p2.unaligned(fb, multi);
-                out |= (uint8_t)(1u << (4 + A2));
-            }
-            const int c11 = p2.newcol(1, 1);
-            int fc = (c00 == c10 && c00 == c01 && c00 == c11) ? c00 : p2.face_colour(c00);
-            out |= (uint8_t)(fc << (1 + A1));
-        }
-        a.flo[q] = out;
-        a.so[D][q] = sd_new;
-        a.so[A1][q] = sa1_new;
-        a.so[A2][q] = sa2_new;
-
-        unsigned long long bal = __ballot((out & 0x70) != 0);
-        if (lane == 0) a.w.bmark[b] = bal != 0;
-        if (__ballot(fb | multi | cfl | merged)) {
-            wave_add(&a.w.stat[ST_FALLBACK], fb);
-            wave_add(&a.w.stat[ST_MULTI], multi);
-            wave_add(&a.w.stat[ST_CFL], cfl);
-            wave_add(&a.w.stat[ST_MERGED], merged);
+        // per-chunk counters (this workgroup owns the chunk)
+        const int f = wave_sum(fbt), m = wave_sum(multit);
+        if (threadIdx.x == 0) {
+            if (f) a.w.cs[CS_FALLBACK * nc + ch] += (unsigned long long)f;
+            if (m) a.w.cs[CS_MULTI * nc + ch] += (unsigned long long)m;
         }
     }
 }
@@ -437,6 +605,177 @@ __device__ __forceinline__ Pt<T> edge_point(int id, T s)
     return {oA, oB, s};
 }
 
+// Reference-phase volume fraction of one cell (sec. 2.5) from its 8 corner
+// flag bytes f[k] (corner k = ox + 2 oy + 4 oz), the 12-bit marker mask `has`
+// and the 12 marker fractions.  Face segments are oriented from the marker
+// where a counter-clockwise walk (about the outward normal) leaves the
+// reference phase to the one where it re-enters; four-marker faces cut off
+// the corners whose colour differs from the face-centre colour.  Loops are
+// the connected sets of segments (separated segments for internal
+// ambiguity, sec. 2.4); each loop is fanned from its marker centroid and the
+// volume follows from Gauss's theorem: (1/3) sum of the phase-1 areas of the
+// three far faces + (1/6) sum over triangles (X_c, X_k+1, X_k) of the triple
+// product.  Returns C; *amb = 1 for a 4-marker face or more than one loop.
+template <typename T>
+__device__ __forceinline__ T cell_volume(const uint8_t f[8], int has, const T sv[12], int &amb_out)
+{
+    int colb = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) colb |= (f[k] & 1) << k;
+    T C;
+    int amb = 0, inter = 0;
+    if (has == 0) {
+        C = (T)(colb & 1);
+    } else {
+        inter = 1;
+        // face segments: oriented from the marker where a counter-clockwise
+        // walk leaves the reference phase to the one where it re-enters
+        uint64_t lab = 0;            // loop label per marker, 4 bits each
+#pragma unroll
+        for (int id = 0; id < 12; ++id) lab |= (uint64_t)id << (4 * id);
+        Pt<T> S = {T(0), T(0), T(0)};
+        T A1[3] = {T(0), T(0), T(0)};
+        int four = 0;
+        // segments kept for the multi-loop path: start/end edge ids
+        int segs = 0;
+        uint8_t sst[12], sen[12];
+#pragma unroll
+        for (int fc = 0; fc < 6; ++fc) {
+            int cl[4], mk[4], ex[4], ed[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                cl[m] = (colb >> kTab.corner[fc][m]) & 1;
+                ed[m] = kTab.edge[fc][m];
+                mk[m] = (has >> ed[m]) & 1;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) ex[m] = cl[m] & (cl[(m + 1) & 3] ^ 1);
+            int cnt = mk[0] + mk[1] + mk[2] + mk[3];
+            int ns = 0, st[2] = {0, 0}, en[2] = {0, 0};
+            if (cnt == 2) {
+                int xs = 0, xe = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (mk[m]) { if (ex[m]) xs = m; else xe = m; }
+                st[0] = xs; en[0] = xe; ns = 1;
+            } else if (cnt == 4) {
+                four = 1;
+                const int a_ = kTab.axis[fc];
+                const int kf = kTab.upper[fc] ? (a_ == 0 ? 1 : (a_ == 1 ? 2 : 4)) : 0;
+                const int ff = (f[kf] >> (1 + a_)) & 1;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (cl[m] == ff) continue;
+                    int mb = (m + 3) & 3;
+                    st[ns] = ex[mb] ? mb : m;
+                    en[ns] = ex[mb] ? m : mb;
+                    ++ns;
+                }
+            }
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (k >= ns) continue;
+                int is = ed[0], ie = ed[0];
+                T ss = sv[ed[0]], se = sv[ed[0]];
+#pragma unroll
+                for (int m = 1; m < 4; ++m) {
+                    if (st[k] == m) { is = ed[m]; ss = sv[ed[m]]; }
+                    if (en[k] == m) { ie = ed[m]; se = sv[ed[m]]; }
+                }
+                Pt<T> Ps = edge_point<T>(is, ss), Pe = edge_point<T>(ie, se);
+                // X_end x X_start (fan orientation of sec. 2.5)
+                S.x += Pe.y * Ps.z - Pe.z * Ps.y;
+                S.y += Pe.z * Ps.x - Pe.x * Ps.z;
+                S.z += Pe.x * Ps.y - Pe.y * Ps.x;
+                if (kTab.upper[fc]) {
+                    const int a_ = kTab.axis[fc];
+                    const int bb = (a_ + 1) % 3, cc = (a_ + 2) % 3;
+                    T us = bb == 0 ? Ps.x : (bb == 1 ? Ps.y : Ps.z);
+                    T vs = cc == 0 ? Ps.x : (cc == 1 ? Ps.y : Ps.z);
+                    T ue = bb == 0 ? Pe.x : (bb == 1 ? Pe.y : Pe.z);
+                    T ve = cc == 0 ? Pe.x : (cc == 1 ? Pe.y : Pe.z);
+                    acc += us * ve - ue * vs;
+                }
+                // merge loop labels
+                uint64_t la = (lab >> (4 * is)) & 15, lb = (lab >> (4 * ie)) & 15;
+                if (la != lb) {
+                    uint64_t keep = la < lb ? la : lb, drop = la < lb ? lb : la;
+#pragma unroll
+                    for (int id = 0; id < 12; ++id)
+                        if (((lab >> (4 * id)) & 15) == drop) lab = (lab & ~(15ull << (4 * id))) | (keep << (4 * id));
+                }
+                sst[segs] = (uint8_t)is;
+                sen[segs] = (uint8_t)ie;
+                ++segs;
+            }
+            if (kTab.upper[fc]) {
+                // phase-1 area of the far face (Green): right side u = 1 is
+                // edge 1, top side v = 1 is edge 2 of the counter-clockwise walk
+                T Lr = mk[1] ? (cl[1] ? sv[ed[1]] : T(1) - sv[ed[1]]) : (T)cl[1];
+                T Lt = mk[2] ? (cl[3] ? sv[ed[2]] : T(1) - sv[ed[2]]) : (T)cl[3];
+                A1[kTab.axis[fc]] = T(0.5) * ((Lr + Lt) + acc);
+            }
+        }
+        // loops: count the roots (markers labelled with their own id)
+        int nloops = 0;
+#pragma unroll
+        for (int id = 0; id < 12; ++id)
+            if (((has >> id) & 1) && ((lab >> (4 * id)) & 15) == (uint64_t)id) ++nloops;
+        T fan = T(0);
+        if (nloops == 1) {
+            T gx = T(0), gy = T(0), gz = T(0);
+            int nm = 0;
+#pragma unroll
+            for (int id = 0; id < 12; ++id) {
+                if (!((has >> id) & 1)) continue;
+                Pt<T> P = edge_point<T>(id, sv[id]);
+                gx += P.x; gy += P.y; gz += P.z;
+                ++nm;
+            }
+            gx = gx / (T)nm; gy = gy / (T)nm; gz = gz / (T)nm;
+            fan = gx * S.x + gy * S.y + gz * S.z;
+        } else {
+            // separated loops (sec. 2.4): one centroid per loop
+#pragma unroll
+            for (int r = 0; r < 12; ++r) {
+                if (!((has >> r) & 1) || ((lab >> (4 * r)) & 15) != (uint64_t)r) continue;
+                T gx = T(0), gy = T(0), gz = T(0);
+                int nm = 0;
+#pragma unroll
+                for (int id = 0; id < 12; ++id) {
+                    if (!((has >> id) & 1) || ((lab >> (4 * id)) & 15) != (uint64_t)r) continue;
+                    Pt<T> P = edge_point<T>(id, sv[id]);
+                    gx += P.x; gy += P.y; gz += P.z;
+                    ++nm;
+                }
+                gx = gx / (T)nm; gy = gy / (T)nm; gz = gz / (T)nm;
+                Pt<T> Sr = {T(0), T(0), T(0)};
+                for (int k = 0; k < segs; ++k) {
+                    int is = sst[k], ie = sen[k];
+                    if (((lab >> (4 * is)) & 15) != (uint64_t)r) continue;
+                    T ss = T(0), se = T(0);
+#pragma unroll
+                    for (int id = 0; id < 12; ++id) {
+                        if (id == is) ss = sv[id];
+                        if (id == ie) se = sv[id];
+                    }
+                    Pt<T> Ps = edge_point<T>(is, ss), Pe = edge_point<T>(ie, se);
+                    Sr.x += Pe.y * Ps.z - Pe.z * Ps.y;
+                    Sr.y += Pe.z * Ps.x - Pe.x * Ps.z;
+                    Sr.z += Pe.x * Ps.y - Pe.y * Ps.x;
+                }
+                fan += gx * Sr.x + gy * Sr.y + gz * Sr.z;
+            }
+        }
+        C = ((A1[0] + A1[1]) + A1[2]) / T(3) + fan / T(6);
+        amb = four || nloops > 1;
+    }
+    amb_out = amb;
+    (void)inter;
+    return C;
+}
+
 template <typename T>
 struct F2VArgs {
     Geo g;
@@ -444,208 +783,135 @@ struct F2VArgs {
     const T *s[3];
     T *C;
     Work w;
-    int slot;
+    uint32_t gen;     // this Front2VOF's generation
+    int full;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_f2v(F2VArgs<T> a)
+// load the 8 corner flag bytes of cell q (corner k = ox + 2 oy + 4 oz)
+__device__ __forceinline__ void corner_flags(const uint8_t *__restrict__ fl, int n, long nn, int x, int y, int z,
+                                             uint8_t f[8], long qc[8])
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * kWavesPerBlock;
-    const int nbr = a.g.nb1 * a.g.nb1 * a.g.nb1;
-    const int count = min((int)a.w.cnt[a.slot], nbr);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.w.cnt[a.slot ^ 1] = 0;
-    const int n = a.g.n;
-    for (int t = wave; t < count; t += nwaves) {
-        const int b = a.w.list[t];
-        if ((unsigned)b >= (unsigned)nbr) continue;
-        int x, y, z;
-        brick_node(a.g, b, lane, x, y, z);
-        const int x1 = x + 1 == n ? 0 : x + 1, y1 = y + 1 == n ? 0 : y + 1, z1 = z + 1 == n ? 0 : z + 1;
-        const long nn = a.g.nn;
-        long qc[8];
-        qc[0] = x + (long)n * y + nn * z;
-        qc[1] = x1 + (long)n * y + nn * z;
-        qc[2] = x + (long)n * y1 + nn * z;
-        qc[3] = x1 + (long)n * y1 + nn * z;
-        qc[4] = x + (long)n * y + nn * z1;
-        qc[5] = x1 + (long)n * y + nn * z1;
-        qc[6] = x + (long)n * y1 + nn * z1;
-        qc[7] = x1 + (long)n * y1 + nn * z1;
-        uint8_t f[8];
+    const int x1 = x + 1 == n ? 0 : x + 1, y1 = y + 1 == n ? 0 : y + 1, z1 = z + 1 == n ? 0 : z + 1;
+    qc[0] = x + (long)n * y + nn * z;
+    qc[1] = x1 + (long)n * y + nn * z;
+    qc[2] = x + (long)n * y1 + nn * z;
+    qc[3] = x1 + (long)n * y1 + nn * z;
+    qc[4] = x + (long)n * y + nn * z1;
+    qc[5] = x1 + (long)n * y + nn * z1;
+    qc[6] = x + (long)n * y1 + nn * z1;
+    qc[7] = x1 + (long)n * y1 + nn * z1;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = a.fl[qc[k]];
-        int colb = 0;
+    for (int k = 0; k < 8; ++k) f[k] = fl[qc[k]];
+}
+
+// 12-bit marker mask of a cell; edge id 4e + oA + 2 oB starts at the corner
+// with offsets oA, oB along the two other axes A < B
+__device__ __forceinline__ int marker_mask(const uint8_t f[8])
+{
+    int has = 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) colb |= (f[k] & 1) << k;
-        // edges: id 4e + oA + 2 oB starts at corner with offset oA, oB
-        int has = 0;
-        T sv[12];
-#pragma unroll
-        for (int id = 0; id < 12; ++id) {
-            int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
-            int ox = e == 0 ? 0 : oA, oy = e == 1 ? 0 : (e == 0 ? oA : oB), oz = e == 2 ? 0 : oB;
-            int k = ox + 2 * oy + 4 * oz;
-            int hb = (f[k] >> (4 + e)) & 1;
-            has |= hb << id;
-            sv[id] = hb ? a.s[e][qc[k]] : T(0);
-        }
-        T C;
-        int amb = 0, inter = 0;
-        if (has == 0) {
-            C = (T)(colb & 1);
-        } else {
-            inter = 1;
-            // face segments: oriented from the marker where a counter-clockwise
-            // walk leaves the reference phase to the one where it re-enters
-            uint64_t lab = 0;            // loop label per marker, 4 bits each
-#pragma unroll
-            for (int id = 0; id < 12; ++id) lab |= (uint64_t)id << (4 * id);
-            Pt<T> S = {T(0), T(0), T(0)};
-            T A1[3] = {T(0), T(0), T(0)};
-            int four = 0;
-            // segments kept for the multi-loop path: start/end edge ids
-            int segs = 0;
-            uint8_t sst[12], sen[12];
-#pragma unroll
-            for (int fc = 0; fc < 6; ++fc) {
-                int cl[4], mk[4], ex[4], ed[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    cl[m] = (colb >> kTab.corner[fc][m]) & 1;
-                    ed[m] = kTab.edge[fc][m];
-                    mk[m] = (has >> ed[m]) & 1;
-                }
-#pragma unroll
-                for (int m = 0; m < 4; ++m) ex[m] = cl[m] & (cl[(m + 1) & 3] ^ 1);
-                int cnt = mk[0] + mk[1] + mk[2] + mk[3];
-                int ns = 0, st[2] = {0, 0}, en[2] = {0, 0};
-                if (cnt == 2) {
-                    int xs = 0, xe = 0;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        if (mk[m]) { if (ex[m]) xs = m; else xe = m; }
-                    st[0] = xs; en[0] = xe; ns = 1;
-                } else if (cnt == 4) {
-                    four = 1;
-                    const int a_ = kTab.axis[fc];
-                    const int kf = kTab.upper[fc] ? (a_ == 0 ? 1 : (a_ == 1 ? 2 : 4)) : 0;
-                    const int ff = (f[kf] >> (1 + a_)) & 1;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        if (cl[m] == ff) continue;
-                        int mb = (m + 3) & 3;
-                        st[ns] = ex[mb] ? mb : m;
-                        en[ns] = ex[mb] ? m : mb;
-                        ++ns;
-                    }
-                }
-                T acc = T(0);
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    if (k >= ns) continue;
-                    int is = ed[0], ie = ed[0];
-                    T ss = sv[ed[0]], se = sv[ed[0]];
-#pragma unroll
-                    for (int m = 1; m < 4; ++m) {
-                        if (st[k] == m) { is = ed[m]; ss = sv[ed[m]]; }
-                        if (en[k] == m) { ie = ed[m]; se = sv[ed[m]]; }
-                    }
-                    Pt<T> Ps = edge_point<T>(is, ss), Pe = edge_point<T>(ie, se);
-                    // X_end x X_start (fan orientation of sec. 2.5)
-                    S.x += Pe.y * Ps.z - Pe.z * Ps.y;
-                    S.y += Pe.z * Ps.x - Pe.x * Ps.z;
-                    S.z += Pe.x * Ps.y - Pe.y * Ps.x;
-                    if (kTab.upper[fc]) {
-                        const int a_ = kTab.axis[fc];
-                        const int bb = (a_ + 1) % 3, cc = (a_ + 2) % 3;
-                        T us = bb == 0 ? Ps.x : (bb == 1 ? Ps.y : Ps.z);
-                        T vs = cc == 0 ? Ps.x : (cc == 1 ? Ps.y : Ps.z);
-                        T ue = bb == 0 ? Pe.x : (bb == 1 ? Pe.y : Pe.z);
-                        T ve = cc == 0 ? Pe.x : (cc == 1 ? Pe.y : Pe.z);
-                        acc += us * ve - ue * vs;
-                    }
-                    // merge loop labels
-                    uint64_t la = (lab >> (4 * is)) & 15, lb = (lab >> (4 * ie)) & 15;
-                    if (la != lb) {
-                        uint64_t keep = la < lb ? la : lb, drop = la < lb ? lb : la;
-#pragma unroll
-                        for (int id = 0; id < 12; ++id)
-                            if (((lab >> (4 * id)) & 15) == drop) lab = (lab & ~(15ull << (4 * id))) | (keep << (4 * id));
-                    }
-                    sst[segs] = (uint8_t)is;
-                    sen[segs] = (uint8_t)ie;
-                    ++segs;
-                }
-                if (kTab.upper[fc]) {
-                    // phase-1 area of the far face (Green): right side u = 1 is
-                    // edge 1, top side v = 1 is edge 2 of the counter-clockwise walk
-                    T Lr = mk[1] ? (cl[1] ? sv[ed[1]] : T(1) - sv[ed[1]]) : (T)cl[1];
-                    T Lt = mk[2] ? (cl[3] ? sv[ed[2]] : T(1) - sv[ed[2]]) : (T)cl[3];
-                    A1[kTab.axis[fc]] = T(0.5) * ((Lr + Lt) + acc);
-                }
+    for (int id = 0; id < 12; ++id) {
+        int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
+        int cx = e == 0 ? 0 : oA, cy = e == 1 ? 0 : (e == 0 ? oA : oB), cz = e == 2 ? 0 : oB;
+        has |= ((f[cx + 2 * cy + 4 * cz] >> (4 + e)) & 1) << id;
+    }
+    return has;
+}
+
+// Front2VOF phase A, one 64-lane workgroup per chunk: a cell of a brick to
+// revisit that carries no marker is full or empty (its corner colour); the
+// others go to the chunk's interfacial-cell segment.
+template <typename T>
+__global__ __launch_bounds__(64) void k_f2v_a(F2VArgs<T> a)
+{
+    const int lane = threadIdx.x;
+    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb, nc = a.g.nc;
+    const long nn = a.g.nn;
+    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+        bool valid;
+        const int bl = chunk_brick(a.g, ch, lane, valid);
+        const bool act = valid && (a.full || a.w.fmark[bl] == a.gen);
+        unsigned long long pending = __ballot(act);
+        int np = 0;
+        long long delta = 0;    // change of the chunk's interfacial-cell count
+        while (pending) {
+            const int k = __ffsll((long long)pending) - 1;
+            pending &= pending - 1;
+            const int b = __shfl(bl, k);
+            const int x = (b % nb1) * 4 + (lane & 3), y = ((b / nb1) % nb1) * 4 + ((lane >> 2) & 3),
+                      z = (b / (nb1 * nb1)) * 4 + (lane >> 4);
+            uint8_t f[8];
+            long qc[8];
+            corner_flags(a.fl, n, nn, x, y, z, f, qc);
+            const int has = marker_mask(f);
+            if (!has) a.C[qc[0]] = (T)(f[0] & 1);
+            wave_put(a.w.ctask + (size_t)ch * kSeg, np, has != 0, (uint32_t)qc[0]);
+            const int nb_int = __popcll(__ballot(has != 0));
+            if (lane == 0) {
+                delta += (long long)nb_int - (long long)a.w.bcnt[b];
+                a.w.bcnt[b] = (uint32_t)nb_int;
             }
-            // loops: count the roots (markers labelled with their own id)
-            int nloops = 0;
+        }
+        if (lane == 0) {
+            a.w.ccnt[ch] = (uint32_t)np;
+            unsigned long long cur = (unsigned long long)((long long)a.w.cs[CS_INTER * nc + ch] + delta);
+            a.w.cs[CS_INTER * nc + ch] = cur;
+            a.w.cs[CS_INTER_SUM * nc + ch] += cur;
+        }
+    }
+}
+
+// Front2VOF phase B: one interfacial cell per lane.
+template <typename T>
+__global__ __launch_bounds__(64) void k_f2v_b(F2VArgs<T> a)
+{
+    const int n = a.g.n, nc = a.g.nc;
+    const long nn = a.g.nn;
+    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
+        int ambc = 0;
+        for (uint32_t i = threadIdx.x; i < count; i += 64) {
+            const long q = (long)a.w.ctask[(size_t)ch * kSeg + i];
+            const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
+            uint8_t f[8];
+            long qc[8];
+            corner_flags(a.fl, n, nn, x, y, z, f, qc);
+            const int has = marker_mask(f);
+            T sv[12];
 #pragma unroll
-            for (int id = 0; id < 12; ++id)
-                if (((has >> id) & 1) && ((lab >> (4 * id)) & 15) == (uint64_t)id) ++nloops;
-            T fan = T(0);
-            if (nloops == 1) {
-                T gx = T(0), gy = T(0), gz = T(0);
-                int nm = 0;
-#pragma unroll
-                for (int id = 0; id < 12; ++id) {
-                    if (!((has >> id) & 1)) continue;
-                    Pt<T> P = edge_point<T>(id, sv[id]);
-                    gx += P.x; gy += P.y; gz += P.z;
-                    ++nm;
-                }
-                gx = gx / (T)nm; gy = gy / (T)nm; gz = gz / (T)nm;
-                fan = gx * S.x + gy * S.y + gz * S.z;
-            } else {
-                // separated loops (sec. 2.4): one centroid per loop
-#pragma unroll
-                for (int r = 0; r < 12; ++r) {
-                    if (!((has >> r) & 1) || ((lab >> (4 * r)) & 15) != (uint64_t)r) continue;
-                    T gx = T(0), gy = T(0), gz = T(0);
-                    int nm = 0;
-#pragma unroll
-                    for (int id = 0; id < 12; ++id) {
-                        if (!((has >> id) & 1) || ((lab >> (4 * id)) & 15) != (uint64_t)r) continue;
-                        Pt<T> P = edge_point<T>(id, sv[id]);
-                        gx += P.x; gy += P.y; gz += P.z;
-                        ++nm;
-                    }
-                    gx = gx / (T)nm; gy = gy / (T)nm; gz = gz / (T)nm;
-                    Pt<T> Sr = {T(0), T(0), T(0)};
-                    for (int k = 0; k < segs; ++k) {
-                        int is = sst[k], ie = sen[k];
-                        if (((lab >> (4 * is)) & 15) != (uint64_t)r) continue;
-                        T ss = T(0), se = T(0);
-#pragma unroll
-                        for (int id = 0; id < 12; ++id) {
-                            if (id == is) ss = sv[id];
-                            if (id == ie) se = sv[id];
-                        }
-                        Pt<T> Ps = edge_point<T>(is, ss), Pe = edge_point<T>(ie, se);
-                        Sr.x += Pe.y * Ps.z - Pe.z * Ps.y;
-                        Sr.y += Pe.z * Ps.x - Pe.x * Ps.z;
-                        Sr.z += Pe.x * Ps.y - Pe.y * Ps.x;
-                    }
-                    fan += gx * Sr.x + gy * Sr.y + gz * Sr.z;
-                }
+            for (int id = 0; id < 12; ++id) {
+                int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
+                int cx = e == 0 ? 0 : oA, cy = e == 1 ? 0 : (e == 0 ? oA : oB), cz = e == 2 ? 0 : oB;
+                sv[id] = ((has >> id) & 1) ? a.s[e][qc[cx + 2 * cy + 4 * cz]] : T(0);
             }
-            C = ((A1[0] + A1[1]) + A1[2]) / T(3) + fan / T(6);
-            amb = four || nloops > 1;
+            int amb = 0;
+            a.C[q] = cell_volume<T>(f, has, sv, amb);
+            ambc += amb;
         }
-        a.C[qc[0]] = C;
-        if (__ballot(inter)) {
-            wave_add(&a.w.stat[ST_INTERFACIAL], inter);
-            wave_add(&a.w.stat[ST_INTER_SUM], inter);
-            wave_add(&a.w.stat[ST_AMBIG], amb);
-        }
+        const int s = wave_sum(ambc);
+        if (threadIdx.x == 0) a.w.cs[CS_AMB * nc + ch] = (unsigned long long)s;
+    }
+}
+
+// totals of the per-chunk counters (integer sums: order-free)
+__global__ __launch_bounds__(256) void k_stats_reduce(Work w, Geo g)
+{
+    __shared__ unsigned long long red[CS_COUNT][4];
+    unsigned long long acc[CS_COUNT];
+    for (int k = 0; k < CS_COUNT; ++k) acc[k] = 0;
+    for (int ch = threadIdx.x; ch < g.nc; ch += blockDim.x)
+        for (int k = 0; k < CS_COUNT; ++k) acc[k] += w.cs[k * g.nc + ch];
+    for (int k = 0; k < CS_COUNT; ++k) {
+        unsigned long long v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < CS_COUNT) {
+        const int k = threadIdx.x;
+        unsigned long long v = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+        const int map[CS_COUNT] = {ST_FALLBACK, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB};
+        w.stat[map[k]] = v;
     }
 }
 
@@ -737,11 +1003,13 @@ struct ebit_ctx {
     int cur;
     Work w;
     Geo g;
-    int nbricks;
-    int seq;            // compaction sequence number: list counter slot = seq & 1
-    int full;           // process every brick
-    const void *lastC;  // C array of the previous Front2VOF
-    int grid_waves;     // persistent grid size (waves)
+    uint32_t t;            // next sweep's sequence number (the first sweep is 2)
+    uint32_t fgen;         // next Front2VOF generation
+    uint32_t last_t_f2v;   // sweep counter at the last Front2VOF
+    int full;              // process every brick
+    const void *lastC;     // C array of the previous Front2VOF
+    int grid_a;            // phase-A grid (64-lane workgroups)
+    int grid_b;            // phase-B grid (256-lane blocks)
 };
 
 namespace {
@@ -758,12 +1026,7 @@ int check_launch()
     return EBIT_OK;
 }
 
-int persistent_blocks(const ebit_ctx *c)
-{
-    int need = (c->nbricks + kWavesPerBlock - 1) / kWavesPerBlock;
-    int cap = c->grid_waves / kWavesPerBlock;
-    return need < cap ? (need > 0 ? need : 1) : cap;
-}
+int clampi(int v, int hi) { return v < hi ? (v > 0 ? v : 1) : hi; }
 
 template <typename T, int D>
 void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
@@ -779,23 +1042,22 @@ void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
     a.U = (const T *)U;
     a.c = cf;
     a.w = c->w;
-    a.slot = c->seq & 1;
-    hipLaunchKernelGGL((k_sweep<T, D>), dim3(persistent_blocks(c)), dim3(kBlock), 0, st, a);
+    a.t = c->t;
+    a.fgen = c->fgen;
+    a.full = c->full;
+    hipLaunchKernelGGL((k_sweep_a<T, D>), dim3(clampi(c->g.nc, c->grid_a)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_sweep_b<T, D>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
 }
 
 template <typename T>
 int sweep_impl(ebit_ctx *c, int dir, const void *U, double g, double dt, hipStream_t st)
 {
-    // compaction of this sweep's bricks
-    int slot = c->seq & 1;
-    hipLaunchKernelGGL(k_band_sweep, dim3((c->nbricks + 255) / 256), dim3(256), 0, st, c->g, c->w, c->nbricks, slot,
-                       c->full);
     double cd = (dt * (double)c->n) * g;
     T cf = (T)cd;
     if (dir == 0) launch_sweep<T, 0>(c, U, cf, st);
     else if (dir == 1) launch_sweep<T, 1>(c, U, cf, st);
     else launch_sweep<T, 2>(c, U, cf, st);
-    c->seq++;
+    c->t++;
     c->cur ^= 1;
     return check_launch();
 }
@@ -804,18 +1066,19 @@ template <typename T>
 int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
 {
     int full = c->full || C != c->lastC;
-    int slot = c->seq & 1;
-    hipLaunchKernelGGL(k_band_f2v, dim3((c->nbricks + 255) / 256), dim3(256), 0, st, c->g, c->w, c->nbricks, slot, full);
+    if (!full && c->last_t_f2v == c->t) return EBIT_OK;   // nothing moved since the last call
     F2VArgs<T> a;
     a.g = c->g;
     a.fl = c->flags[c->cur];
     for (int e = 0; e < 3; ++e) a.s[e] = (const T *)c->s[c->cur][e];
     a.C = (T *)C;
     a.w = c->w;
-    a.slot = slot;
-    hipLaunchKernelGGL((k_f2v<T>), dim3(persistent_blocks(c)), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_clear_touched, dim3((c->nbricks + 255) / 256), dim3(256), 0, st, c->w, c->nbricks);
-    c->seq++;
+    a.gen = c->fgen;
+    a.full = full;
+    hipLaunchKernelGGL((k_f2v_a<T>), dim3(clampi(c->g.nc, c->grid_a)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_f2v_b<T>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
+    c->fgen++;
+    c->last_t_f2v = c->t;
     c->lastC = C;
     return check_launch();
 }
@@ -873,11 +1136,24 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->g.n = d->n;
     c->g.nb1 = d->n / 4;
     c->g.nn = (long)d->n * d->n;
-    c->nbricks = c->g.nb1 * c->g.nb1 * c->g.nb1;
-    c->seq = 0;
+    int nbricks = c->g.nb1 * c->g.nb1 * c->g.nb1;
+    c->g.nb = nbricks;
+    c->g.nc = chunks_for(d->n);
+    {
+        // hash multiplier: a prime above the brick count (hence coprime with it)
+        long p = 1000003;
+        while (p <= nbricks) p = p * 2 + 1;
+        auto isprime = [](long v) { for (long q = 3; q * q <= v; q += 2) if (v % q == 0) return false; return (v & 1) != 0; };
+        while (!isprime(p)) p += 2;
+        c->g.hmul = p % nbricks == 0 ? 1 : p;
+    }
+    c->t = 2;
+    c->fgen = 1;
+    c->last_t_f2v = 0;
     c->full = 0;
     c->lastC = nullptr;
-    c->grid_waves = 256 * 16;   // 16 waves per CU across 256 CUs
+    c->grid_a = 256 * 24;       // persistent: 24 single-wave workgroups per CU
+    c->grid_b = 256 * 16;       // 16 single-wave workgroups per CU
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
@@ -901,8 +1177,8 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
         free(c);
         return EBIT_EHIP;
     }
-    hipLaunchKernelGGL(k_mark_all, dim3((c->nbricks + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, st,
-                       c->g, c->flags[0], c->w, c->nbricks);
+    hipLaunchKernelGGL(k_zero_work, dim3((c->g.nb + 255) / 256), dim3(256), 0, st, c->w, c->g);
+    hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, c->grid_a)), dim3(64), 0, st, c->g, c->flags[0], c->w);
     int rc = check_launch();
     if (rc != EBIT_OK) {
         free(c);
@@ -933,6 +1209,7 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     hipStream_t st = S(stream);
     long N = (long)c->n * c->n * c->n;
     hipLaunchKernelGGL(k_zero_marks, dim3(1), dim3(64), 0, st, c->w.stat);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, c->w, c->g);
     if (c->precision == EBIT_FP64)
         hipLaunchKernelGGL(k_vol_partial<double>, dim3(kRedBlocks - 1), dim3(256), 0, st, (const double *)C,
                            c->flags[c->cur], N, c->w.part, c->w.stat);
@@ -951,8 +1228,8 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     if (hipStreamSynchronize(st) != hipSuccess) return EBIT_EHIP;
     out->volume = vol[0];
     out->volume_comp = vol[1];
-    out->n_interfacial = (int64_t)stat[ST_INTERFACIAL];
-    out->n_ambiguous = (int64_t)stat[ST_AMBIG];
+    out->n_interfacial = c->fgen > 1 ? (int64_t)stat[ST_INTER] : 0;
+    out->n_ambiguous = c->fgen > 1 ? (int64_t)stat[ST_AMB] : 0;
     out->n_markers[0] = (int64_t)stat[ST_MARK0];
     out->n_markers[1] = (int64_t)stat[ST_MARK1];
     out->n_markers[2] = (int64_t)stat[ST_MARK2];
@@ -961,7 +1238,7 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     out->n_cfl = (int64_t)stat[ST_CFL];
     out->n_merged = (int64_t)stat[ST_MERGED];
     out->n_active_cells = (int64_t)stat[ST_ACTIVE];
-    out->step_sweeps = (int64_t)stat[ST_SWEEPS];
+    out->step_sweeps = (int64_t)(c->t - 2);
     out->n_interfacial_sum = (int64_t)stat[ST_INTER_SUM];
     return out->n_cfl ? EBIT_ECFL : EBIT_OK;
 }

@@ -94,111 +94,64 @@ __device__ __forceinline__ T fit_height(T P1x, T P1y, T P2x, T P2y, T P3x, T P3y
 }
 
 // One 2D problem of a sweep (paper sec. 2.3): the plane spanned by the sweep
-// axis D ("X") and axis A ("Y") through the thread's node.  Offsets (i, j) are
-// relative to that node.  Horizontal edges H(i,j) run along D (aligned
-// markers), vertical edges V(i,j) along A (unaligned); face Q(i,j) spans
-// [i,i+1] x [j,j+1] and has normal B.
-template <typename T, int D, int A>
-struct Plane {
+// axis D ("X") and axis A ("Y") through a node.  Offsets (i, j) are relative
+// to that node.  Horizontal edges H(i,j) run along D (aligned markers),
+// vertical edges V(i,j) along A (unaligned); face Q(i,j) spans [i,i+1] x
+// [j,j+1] and has normal B.  The accessor `Acc` supplies, per node offset:
+//   f(i,j)    old flags (bit 7: the node's new colour after this sweep)
+//   xd(i,j)   s + delta of the D-edge marker (decision precision, double)
+//   dva(i,j)  delta of the A-edge marker (double)
+//   sa(i,j)   fraction of the A-edge marker
+template <typename T, int D, int A, class Acc>
+struct PlaneAlg {
     static constexpr int B = 3 - D - A;
-    const uint8_t *__restrict__ fl;
-    const T *__restrict__ sD;
-    const T *__restrict__ sA;
-    const T *__restrict__ U;
-    T c;             // (dt n) g: cell-unit displacement per unit velocity
-    int n;
-    int ci, cj;      // coordinates of the thread's node along D and A
-    long base;       // index part of the fixed coordinate along B
-    long strD, strA;
+    Acc acc;
 
-    __device__ __forceinline__ long node(int i, int j) const
-    {
-        return (long)wrp(ci + i, n) * strD + (long)wrp(cj + j, n) * strA + base;
-    }
-    __device__ __forceinline__ uint8_t f(int i, int j) const { return fl[node(i, j)]; }
-    __device__ __forceinline__ int col(int i, int j) const { return f(i, j) & 1; }
-    __device__ __forceinline__ bool hhas(int i, int j) const { return (f(i, j) >> (4 + D)) & 1; }
-    __device__ __forceinline__ bool vhas(int i, int j) const { return (f(i, j) >> (4 + A)) & 1; }
+    __device__ __forceinline__ uint8_t f(int i, int j) const { return acc.f(i, j); }
+    __device__ __forceinline__ int ncol(int i, int j) const { return (acc.f(i, j) >> 7) & 1; }
+    __device__ __forceinline__ bool hhas(int i, int j) const { return (acc.f(i, j) >> (4 + D)) & 1; }
+    __device__ __forceinline__ bool vhas(int i, int j) const { return (acc.f(i, j) >> (4 + A)) & 1; }
 
-    // Euler step (eq. Eq_marker_dis) of the aligned marker on H(i,j): its new
-    // coordinate s + delta relative to node i (decisions in double).
-    __device__ __forceinline__ double xd(int i, int j) const
-    {
-        long q = node(i, j);
-        T s = sD[q];
-        T U0 = U[q];
-        T U1 = U[node(i + 1, j)];
-        T u = U0 + s * (U1 - U0);
-        T delta = c * u;
-        return (double)s + (double)delta;
-    }
-    // displacement of the unaligned marker on V(i,j) (it keeps its Y)
-    __device__ __forceinline__ double dva(int i, int j) const
-    {
-        long q = node(i, j);
-        T s = sA[q];
-        T U0 = U[q];
-        T U1 = U[node(i, j + 1)];
-        T u = U0 + s * (U1 - U0);
-        return (double)(c * u);
-    }
-
-    // new colour of node (i,j): flips once per aligned marker crossing it
-    __device__ __forceinline__ int newcol(int i, int j) const
-    {
-        int cc = col(i, j);
-        if (hhas(i - 1, j) && xd(i - 1, j) >= 1.0) cc ^= 1;
-        if (hhas(i, j) && xd(i, j) < 0.0) cc ^= 1;
-        return cc;
-    }
-
-    // sides of a face: 0 bottom H(fi,fj), 1 right V(fi+1,fj), 2 top H(fi,fj+1), 3 left V(fi,fj)
-    __device__ __forceinline__ bool side_has(int fi, int fj, int side) const
-    {
-        switch (side) {
-        case 0: return hhas(fi, fj);
-        case 1: return vhas(fi + 1, fj);
-        case 2: return hhas(fi, fj + 1);
-        default: return vhas(fi, fj);
-        }
-    }
-
-    // advected marker of a side, relative to the thread's node
+    // advected marker of a side, relative to the reference node
+    // sides: 0 bottom H(fi,fj), 1 right V(fi+1,fj), 2 top H(fi,fj+1), 3 left V(fi,fj)
     __device__ __forceinline__ void point(int fi, int fj, int side, double &X, double &Y) const
     {
         switch (side) {
-        case 0: X = (double)fi + xd(fi, fj); Y = (double)fj; break;
-        case 2: X = (double)fi + xd(fi, fj + 1); Y = (double)(fj + 1); break;
-        case 3: X = (double)fi + dva(fi, fj); Y = (double)fj + (double)sA[node(fi, fj)]; break;
-        default: X = (double)(fi + 1) + dva(fi + 1, fj); Y = (double)fj + (double)sA[node(fi + 1, fj)]; break;
+        case 0: X = (double)fi + acc.xd(fi, fj); Y = (double)fj; break;
+        case 2: X = (double)fi + acc.xd(fi, fj + 1); Y = (double)(fj + 1); break;
+        case 3: X = (double)fi + acc.dva(fi, fj); Y = (double)fj + (double)acc.sa(fi, fj); break;
+        default: X = (double)(fi + 1) + acc.dva(fi + 1, fj); Y = (double)fj + (double)acc.sa(fi + 1, fj); break;
         }
     }
 
-    // segments of face Q(fi,fj) from the old state (paper sec. 2.2, 2.4);
-    // encoded as sides (a0,b0),(a1,b1) with a < b; the one through side 0 first
-    __device__ __forceinline__ int pairs(int fi, int fj, int pr[2][2]) const
+    // segments of face Q(fi,fj) from the old state (paper sec. 2.2, 2.4),
+    // packed: bits 0-1 / 2-3 the sides of the first segment (lower first), bits
+    // 4-5 / 6-7 the second; bits 8-9 the number of segments.  The segment
+    // through side 0 comes first.
+    __device__ __forceinline__ int pairs(int fi, int fj) const
     {
         uint8_t f00 = f(fi, fj), f10 = f(fi + 1, fj), f01 = f(fi, fj + 1);
         int h0 = (f00 >> (4 + D)) & 1, v1 = (f10 >> (4 + A)) & 1;
         int h2 = (f01 >> (4 + D)) & 1, v3 = (f00 >> (4 + A)) & 1;
         int m = h0 + v1 + h2 + v3;
         if (m == 2) {
-            int has[4] = {h0, v1, h2, v3};
-            int k = 0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (has[t]) { pr[0][k] = t; ++k; }
-            return 1;
+            // the two sides present, lower first
+            int lo = h0 ? 0 : (v1 ? 1 : 2);
+            int hi = v3 ? 3 : (h2 ? 2 : 1);
+            return lo | (hi << 2) | (1 << 8);
         }
         if (m == 4) {
             int c00 = f00 & 1;
             int ff = (f00 >> (1 + B)) & 1;
-            if (ff == c00) { pr[0][0] = 0; pr[0][1] = 1; pr[1][0] = 2; pr[1][1] = 3; }
-            else { pr[0][0] = 0; pr[0][1] = 3; pr[1][0] = 1; pr[1][1] = 2; }
-            return 2;
+            // corners (1,0),(0,1) cut off: (0,1),(2,3); else corners (0,0),(1,1): (0,3),(1,2)
+            return ff == c00 ? (0 | (1 << 2) | (2 << 4) | (3 << 6) | (2 << 8))
+                             : (0 | (3 << 2) | (1 << 4) | (2 << 6) | (2 << 8));
         }
         return 0;
     }
+    static __device__ __forceinline__ int nseg(int pk) { return pk >> 8; }
+    static __device__ __forceinline__ int side_a(int pk, int t) { return (pk >> (4 * t)) & 3; }
+    static __device__ __forceinline__ int side_b(int pk, int t) { return (pk >> (4 * t + 2)) & 3; }
 
     // far end, in the neighbouring face, of the segment through `side`'s marker
     __device__ __forceinline__ void neighbour(int fi, int fj, int side, double &X, double &Y) const
@@ -210,12 +163,13 @@ struct Plane {
         case 1: ni = fi + 1; ns = 3; break;
         default: ni = fi - 1; ns = 1; break;
         }
-        int pr[2][2];
-        int k = pairs(ni, nj, pr);
+        int pk = pairs(ni, nj);
         int other = ns;
-        for (int t = 0; t < k; ++t) {
-            if (pr[t][0] == ns) other = pr[t][1];
-            else if (pr[t][1] == ns) other = pr[t][0];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t >= nseg(pk)) break;
+            if (side_a(pk, t) == ns) other = side_b(pk, t);
+            else if (side_b(pk, t) == ns) other = side_a(pk, t);
         }
         point(ni, nj, other, X, Y);
     }
@@ -230,16 +184,15 @@ struct Plane {
         int m = 0;
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
-            int pr[2][2];
-            int k = pairs(o - 2, 0, pr);
+            int pk = pairs(o - 2, 0);
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 ok[2 * o + t] = false;
                 key[2 * o + t] = T(0);
-                if (t < k) {
+                if (t < nseg(pk)) {
                     double Ax, Ay, Bx, By;
-                    point(o - 2, 0, pr[t][0], Ax, Ay);
-                    point(o - 2, 0, pr[t][1], Bx, By);
+                    point(o - 2, 0, side_a(pk, t), Ax, Ay);
+                    point(o - 2, 0, side_b(pk, t), Bx, By);
                     bool sa = 0.0 <= Ax, sb = 0.0 <= Bx;
                     if (sa != sb) {
                         ok[2 * o + t] = true;
@@ -251,10 +204,10 @@ struct Plane {
             }
         }
         if ((m & 1) == 0) {          // no odd crossing set: keep the edge valid
-            fallback = 1;
+            fallback += 1;
             return T(0.5);
         }
-        if (m > 1) multi = 1;
+        if (m > 1) multi += 1;
         int pick = 0;
 #pragma unroll
         for (int c0 = 0; c0 < 6; ++c0) {
@@ -266,15 +219,15 @@ struct Plane {
             if (rank == (m >> 1)) pick = c0;
         }
         int o = (pick >> 1) - 2, t = pick & 1;
-        int pr[2][2];
-        pairs(o, 0, pr);
+        int pk = pairs(o, 0);
+        int sa_ = side_a(pk, t), sb_ = side_b(pk, t);
         double Ax, Ay, Bx, By;
-        point(o, 0, pr[t][0], Ax, Ay);
-        point(o, 0, pr[t][1], Bx, By);
+        point(o, 0, sa_, Ax, Ay);
+        point(o, 0, sb_, Bx, By);
         int s2, s3;
         double P2x, P2y, P3x, P3y;
-        if (0.0 <= Ax) { s2 = pr[t][1]; s3 = pr[t][0]; P2x = Bx; P2y = By; P3x = Ax; P3y = Ay; }
-        else { s2 = pr[t][0]; s3 = pr[t][1]; P2x = Ax; P2y = Ay; P3x = Bx; P3y = By; }
+        if (0.0 <= Ax) { s2 = sb_; s3 = sa_; P2x = Bx; P2y = By; P3x = Ax; P3y = Ay; }
+        else { s2 = sa_; s3 = sb_; P2x = Ax; P2y = Ay; P3x = Bx; P3y = By; }
         double P1x, P1y, P4x, P4y;
         neighbour(o, 0, s2, P1x, P1y);
         neighbour(o, 0, s3, P4x, P4y);
@@ -291,17 +244,18 @@ struct Plane {
 #pragma unroll
         for (int o = -1; o <= 1; ++o) {
             if (!hhas(o, 0)) continue;
-            double X = (double)o + xd(o, 0);
+            double X = (double)o + acc.xd(o, 0);
             if (0.0 <= X && X < 0.5) par ^= 1;
         }
 #pragma unroll
         for (int o = -1; o <= 1; ++o) {
-            int pr[2][2];
-            int k = pairs(o, 0, pr);
-            for (int t = 0; t < k; ++t) {
+            int pk = pairs(o, 0);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (t >= nseg(pk)) break;
                 double Ax, Ay, Bx, By;
-                point(o, 0, pr[t][0], Ax, Ay);
-                point(o, 0, pr[t][1], Bx, By);
+                point(o, 0, side_a(pk, t), Ax, Ay);
+                point(o, 0, side_b(pk, t), Bx, By);
                 bool sa = 0.5 <= Ax, sb = 0.5 <= Bx;
                 if (sa == sb) continue;
                 T y = sa ? line_cross<T>(T(0.5), (T)Bx, (T)By, (T)Ax, (T)Ay)
