@@ -43,8 +43,64 @@ def parse():
     p.add_argument("--n", type=int, default=256)
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp32", action="store_true", help="skip the FP32 precision-form run")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
+
+
+def run_case(E, I, torch, n, precision, W, K, events):
+    """W untimed steps, then K timed steps of the deformation workload."""
+    T_end = 3.0
+    dt = 0.5 / n
+    dev = torch.device("cuda:0")
+    sh = I.sphere_shape(n)
+    U = I.deformation_velocity(n)
+    tdev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    Ud = [tdev(u).to(dtype) for u in U]
+    e = E.Ebit(n, precision, dev)
+    e.init(tdev(sh.phi_nodes), [tdev(f) for f in sh.phi_faces])
+    del sh
+    C = torch.zeros((n, n, n), dtype=dtype, device=dev)
+    e.front2vof(C)
+    C0 = C.clone()
+    stream = torch.cuda.current_stream()
+    step = 0
+    for _ in range(W):
+        e.step(Ud, I.deformation_time_factor(step * dt, T_end), dt)
+        e.front2vof(C)
+        step += 1
+    st0 = e.stats(C)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g = I.deformation_time_factor(step * dt, T_end)
+        for d in range(3):
+            if events:
+                s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s_ev.record(stream)
+            e.sweep(d, Ud[d], g, dt)
+            if events:
+                e_ev.record(stream)
+                ev.append(("sweep", s_ev, e_ev))
+        if events:
+            s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_ev.record(stream)
+        e.front2vof(C)
+        if events:
+            e_ev.record(stream)
+            ev.append(("f2v", s_ev, e_ev))
+        step += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st1 = e.stats(C)
+    n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
+    kt = {"sweep": [], "f2v": []}
+    for kind, s_ev, e_ev in ev:
+        kt[kind].append(s_ev.elapsed_time(e_ev) * 1e-3)
+    return {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "kt": kt, "C": C.double(),
+            "C0": C0.double(), "ended_at_T": step == int(round(T_end / dt))}
 
 
 def main():
@@ -58,69 +114,21 @@ def main():
     from paper_2509_26361_amd import inputs as I
 
     n = a.n
-    T_end = 3.0
     dt = 0.5 / n
-    period = int(round(T_end / dt))
+    period = int(round(3.0 / dt))
     K = a.steps if a.steps is not None else period - a.warmup
     W = a.warmup
-    dev = torch.device("cuda:0")
     print(f"[bench] deformation n={n} precision={a.precision} warmup={W} steps={K}", file=sys.stderr, flush=True)
-
-    sh = I.sphere_shape(n)
-    U = I.deformation_velocity(n)
-    tdev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-    dtype = torch.float64 if a.precision == "fp64" else torch.float32
-    Ud = [tdev(u).to(dtype) for u in U]
-    e = E.Ebit(n, a.precision, dev)
-    e.init(tdev(sh.phi_nodes), [tdev(f) for f in sh.phi_faces])
-    C = torch.zeros((n, n, n), dtype=dtype, device=dev)
-    e.front2vof(C)
-    stream = torch.cuda.current_stream()
-
-    step = 0
-    for _ in range(W):
-        g = I.deformation_time_factor(step * dt, T_end)
-        e.step(Ud, g, dt)
-        e.front2vof(C)
-        step += 1
-    st0 = e.stats(C)
-    torch.cuda.synchronize()
-
-    ev = []   # (kind, start, end)
-    t0 = time.perf_counter()
-    for _ in range(K):
-        g = I.deformation_time_factor(step * dt, T_end)
-        for d in range(3):
-            s_ev = torch.cuda.Event(enable_timing=True)
-            e_ev = torch.cuda.Event(enable_timing=True)
-            s_ev.record(stream)
-            e.sweep(d, Ud[d], g, dt)
-            e_ev.record(stream)
-            ev.append(("sweep", s_ev, e_ev))
-        s_ev = torch.cuda.Event(enable_timing=True)
-        e_ev = torch.cuda.Event(enable_timing=True)
-        s_ev.record(stream)
-        e.front2vof(C)
-        e_ev.record(stream)
-        ev.append(("f2v", s_ev, e_ev))
-        step += 1
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = e.stats(C)
-    wall = t1 - t0
-
-    # interfacial cells at the start of each timed step
-    n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
+    r = run_case(E, I, torch, n, a.precision, W, K, events=True)
+    wall, n_start, st0, st1, kt = r["wall"], r["n_start"], r["st0"], r["st1"], r["kt"]
     value = n_start / wall
-    kt = {"sweep": [], "f2v": []}
-    for kind, s_ev, e_ev in ev:
-        kt[kind].append(s_ev.elapsed_time(e_ev) * 1e-3)
     tot = {k: sum(v) for k, v in kt.items()}
     dom = max(tot, key=tot.get)
     avg_dur = tot[dom] / len(kt[dom])
     units_per_launch = n_start / K          # interfacial cells per launch (step-start count)
     bytes_per_launch = BYTES[a.precision][dom] * units_per_launch
     achieved = bytes_per_launch / avg_dur / 1e9
+    e_shape = float((r["C"] - r["C0"]).abs().sum() / r["C0"].sum())
 
     out = {
         "metric": "interfacial cell-updates/s (advect+Front2VOF), 256^3; vol err vs FP64",
@@ -139,7 +147,8 @@ def main():
                                f"CFL 0.5, steps {W}..{W + K} of {period}",
                    "n": n, "precision": a.precision, "sweeps_per_step": 3},
         "roofline": {
-            "kernel": "k_sweep" if dom == "sweep" else "k_f2v",
+            "kernel": "ebit_advect_sweep (k_sweep_a + k_sweep_b)" if dom == "sweep"
+                      else "ebit_front2vof (k_f2v_a + k_f2v_b)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -154,9 +163,29 @@ def main():
         "interfacial_cells": {"start": st0["n_interfacial"], "end": st1["n_interfacial"],
                               "mean": n_start / K},
         "volume": {"start": st0["volume"] + st0["volume_comp"], "end": st1["volume"] + st1["volume_comp"]},
+        "e_shape_at_T": e_shape if r["ended_at_T"] else None,
         "counters": {k: st1[k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged")},
         "band_bricks_per_sweep": (st1["n_active_cells"] - st0["n_active_cells"]) / 64.0 / (3 * K),
     }
+
+    if a.precision == "fp64" and not a.no_fp32:
+        # precision form: same workload in FP32, errors against this FP64 run
+        C64, V64 = r["C"], out["volume"]["end"]
+        del r
+        torch.cuda.empty_cache()
+        q = run_case(E, I, torch, n, "fp32", W, K, events=False)
+        V32 = q["st1"]["volume"] + q["st1"]["volume_comp"]
+        e32 = float((q["C"] - q["C0"]).abs().sum() / q["C0"].sum())
+        out["fp32_form"] = {
+            "value": q["n_start"] / q["wall"],
+            "ms_per_step": q["wall"] / K * 1e3,
+            "volume_rel_err_vs_fp64": abs(V32 - V64) / V64,
+            "max_abs_C_diff_vs_fp64": float((q["C"] - C64).abs().max()),
+            "e_shape_at_T": e32 if q["ended_at_T"] else None,
+            "e_shape_ratio_fp32_over_fp64": (e32 / e_shape) if (q["ended_at_T"] and e_shape > 0) else None,
+        }
+        del q
+        torch.cuda.empty_cache()
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, a.cpu_seconds)
