@@ -147,6 +147,40 @@ int ebit_current(const ebit_ctx *ctx);
 enum { EBIT_OPT_FULL_GRID = 1 };   /* 1: process every cell, not only the band */
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
 
+/* ------------------------------------------------------------------------ *
+ * Learned Front2VOF surrogate (not part of the paper): a multilayer
+ * perceptron 20 -> 128 -> 128 -> 1 (ReLU, ReLU, sigmoid) from a cell's 12
+ * edge-marker fractions (0 where an edge has no marker; edge id 4e + oA + 2 oB
+ * along axis e with offsets oA, oB on the two other axes A < B) and its 8
+ * corner colours (corner k = ox + 2 oy + 4 oz) to its volume fraction.
+ * Parameters: float32 vector of ebit_mlp_param_count() numbers, in order
+ * W1 (20 x 128, row-major in x out), b1 (128), W2 (128 x 128), b2 (128),
+ * w3 (128), b3 (1).  Products run on bfloat16 matrix cores with float32
+ * accumulation; rounding to bfloat16 (nearest, ties to even) happens at the
+ * inputs, W1, W2 and the first hidden layer (forward) and at dz2, dz1
+ * (backward).  Input rows x: bfloat16, 32 per row (features 0..19, then 0).
+ * ------------------------------------------------------------------------ */
+
+/* Number of parameters (19329). */
+int ebit_mlp_param_count(void);
+
+/* Device scratch bytes ebit_mlp_gradient needs. */
+size_t ebit_mlp_scratch_bytes(void);
+
+/* y[i] = network(x row i) for m rows (device pointers).  Async on stream. */
+int ebit_mlp_forward(const float *theta, const void *x_bf16, int64_t m, float *y, void *stream);
+
+/* Gradient of the mean squared error (1/m) sum (y_i - c_i)^2 with respect to
+ * theta into grad (float32, param_count), the loss into *loss (device, may be
+ * NULL).  Partial sums per workgroup are added in a fixed order
+ * (deterministic).  scratch: device, >= ebit_mlp_scratch_bytes(). */
+int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad, float *loss,
+                      void *scratch, size_t scratch_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on theta with first / second moments m1, m2 (float32, param_count each). */
+int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t step, float lr, void *stream);
+
 /* Free the context (not the caller's buffers). */
 void ebit_destroy(ebit_ctx *ctx);
 

@@ -87,6 +87,16 @@ def lib():
         L.ebit_destroy.restype = None
         L.ebit_strerror.argtypes = [ctypes.c_int]
         L.ebit_strerror.restype = ctypes.c_char_p
+        L.ebit_mlp_param_count.argtypes = []
+        L.ebit_mlp_param_count.restype = ctypes.c_int
+        L.ebit_mlp_scratch_bytes.argtypes = []
+        L.ebit_mlp_scratch_bytes.restype = ctypes.c_size_t
+        L.ebit_mlp_forward.argtypes = [P, P, ctypes.c_int64, P, P]
+        L.ebit_mlp_forward.restype = ctypes.c_int
+        L.ebit_mlp_gradient.argtypes = [P, P, P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]
+        L.ebit_mlp_gradient.restype = ctypes.c_int
+        L.ebit_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float, P]
+        L.ebit_mlp_adam.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -211,3 +221,53 @@ class Ebit:
             self._destroy()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# learned Front2VOF surrogate
+# ----------------------------------------------------------------------------
+
+def _check(rc, what):
+    if rc != EBIT_OK:
+        raise EbitError(rc, what)
+
+
+def mlp_param_count() -> int:
+    return lib().ebit_mlp_param_count()
+
+
+def mlp_forward(theta, x_bf16, y=None, stream=None):
+    """theta: float32 device vector; x_bf16: (m, 32) bfloat16 device rows."""
+    m = x_bf16.shape[0]
+    if y is None:
+        y = torch.empty(m, dtype=torch.float32, device=x_bf16.device)
+    _check(lib().ebit_mlp_forward(_ptr(theta), _ptr(x_bf16), m, _ptr(y), _stream(stream)), "ebit_mlp_forward")
+    return y
+
+
+class MlpTrainer:
+    """Device buffers for gradient / Adam steps of the surrogate."""
+
+    def __init__(self, theta, device="cuda"):
+        self.theta = theta
+        n = mlp_param_count()
+        self.m1 = torch.zeros(n, dtype=torch.float32, device=device)
+        self.m2 = torch.zeros(n, dtype=torch.float32, device=device)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.scratch = torch.empty(lib().ebit_mlp_scratch_bytes(), dtype=torch.uint8, device=device)
+        self.t = 0
+
+    def gradient(self, x_bf16, c, stream=None):
+        L = lib()
+        _check(L.ebit_mlp_gradient(_ptr(self.theta), _ptr(x_bf16), _ptr(c), x_bf16.shape[0], _ptr(self.grad),
+                                   _ptr(self.loss), _ptr(self.scratch), self.scratch.numel(), _stream(stream)),
+               "ebit_mlp_gradient")
+        return self.grad, self.loss
+
+    def step(self, x_bf16, c, lr, stream=None):
+        self.gradient(x_bf16, c, stream)
+        self.t += 1
+        _check(lib().ebit_mlp_adam(_ptr(self.theta), _ptr(self.m1), _ptr(self.m2), _ptr(self.grad), self.t,
+                                   float(lr), _stream(stream)), "ebit_mlp_adam")
+        return self.loss

@@ -320,6 +320,16 @@ def random_nonoverlapping_spheres(count, rmin_cells, rmax_cells, n, gap_cells=2.
     return cs, rs
 
 
+def mlp_init(seed, nin=20, nh=128):
+    """Seeded initial parameters of the surrogate network (He-uniform weights,
+    zero biases), in the parameter order W1, b1, W2, b2, w3, b3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.uniform(-1, 1, size=(nin, nh)) * math.sqrt(6.0 / nin)
+    W2 = rng.uniform(-1, 1, size=(nh, nh)) * math.sqrt(6.0 / nh)
+    w3 = rng.uniform(-1, 1, size=nh) * math.sqrt(6.0 / nh) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(nh), W2.ravel(), np.zeros(nh), w3, [0.0]])
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------

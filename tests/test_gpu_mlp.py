@@ -1,0 +1,96 @@
+"""The surrogate's BF16-MFMA kernels against the CPU FP64 oracle run with
+the same bfloat16 rounding points: forward outputs, gradients, Adam."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from paper_2509_26361_amd import ebit as E
+from paper_2509_26361_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_bf16_rows(X):
+    """(m, 20) float64 -> (m, 32) bfloat16 rows on the device (zero padded)."""
+    m = X.shape[0]
+    P = np.zeros((m, 32), dtype=np.float32)
+    P[:, :20] = X
+    return torch.from_numpy(P).to(dev()).to(torch.bfloat16)
+
+
+def theta32(seed):
+    th = I.mlp_init(seed)
+    return th, torch.from_numpy(th.astype(np.float32)).to(dev())
+
+
+@pytest.mark.parametrize("m", [1, 17, 1000, 4099])
+def test_forward_matches_oracle(m):
+    rng = np.random.default_rng(m)
+    th, tg = theta32(1)
+    X = np.concatenate([rng.uniform(0, 1, size=(m, 12)), rng.integers(0, 2, size=(m, 8))], axis=1)
+    y = E.mlp_forward(tg, to_bf16_rows(X)).cpu().numpy()
+    yo = M.forward(th.astype(np.float32).astype(np.float64), X, bf16_mode=True)
+    assert np.max(np.abs(y - yo)) < 2e-3, np.max(np.abs(y - yo))
+    assert np.mean(np.abs(y - yo)) < 2e-4
+
+
+@pytest.mark.parametrize("m", [64, 333, 5000])
+def test_gradient_matches_oracle(m):
+    rng = np.random.default_rng(m + 7)
+    th, tg = theta32(2)
+    th = th.astype(np.float32).astype(np.float64)
+    X = np.concatenate([rng.uniform(0, 1, size=(m, 12)), rng.integers(0, 2, size=(m, 8))], axis=1)
+    c = rng.uniform(0, 1, size=m)
+    tr = E.MlpTrainer(tg, dev())
+    g, loss = tr.gradient(to_bf16_rows(X), torch.from_numpy(c.astype(np.float32)).to(dev()))
+    lo, go = M.loss_and_grad(th, X, c, bf16_mode=True)
+    g = g.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    assert rel < 2e-2, rel
+    # per parameter block
+    o = 0
+    for name, shp in M.SIZES:
+        k = int(np.prod(shp))
+        rb = np.linalg.norm(g[o:o + k] - go[o:o + k]) / (np.linalg.norm(go[o:o + k]) + 1e-30)
+        assert rb < 3e-2, (name, rb)
+        o += k
+    assert abs(float(loss.item()) - lo) < 1e-4 * max(1.0, lo)
+
+
+def test_gradient_is_deterministic():
+    rng = np.random.default_rng(3)
+    _, tg = theta32(3)
+    X = to_bf16_rows(rng.uniform(0, 1, size=(3000, 20)))
+    c = torch.from_numpy(rng.uniform(0, 1, 3000).astype(np.float32)).to(dev())
+    tr = E.MlpTrainer(tg, dev())
+    g1 = tr.gradient(X, c)[0].clone()
+    g2 = tr.gradient(X, c)[0].clone()
+    assert torch.equal(g1, g2)
+
+
+def test_adam_matches_oracle_and_training_reduces_loss():
+    rng = np.random.default_rng(5)
+    th, tg = theta32(4)
+    m = 2048
+    X = np.concatenate([rng.uniform(0, 1, size=(m, 12)), rng.integers(0, 2, size=(m, 8))], axis=1)
+    c = 1.0 / (1.0 + np.exp(-(X[:, :12].sum(axis=1) - 6.0)))        # a smooth target
+    xb = to_bf16_rows(X)
+    cg = torch.from_numpy(c.astype(np.float32)).to(dev())
+    tr = E.MlpTrainer(tg, dev())
+    g = tr.gradient(xb, cg)[0].cpu().numpy().astype(np.float64)
+    th0 = tg.cpu().numpy().astype(np.float64)
+    opt = M.Adam(len(th0), lr=1e-3)
+    want = opt.step(th0, g)
+    tr.t = 1
+    E.lib().ebit_mlp_adam(E._ptr(tr.theta), E._ptr(tr.m1), E._ptr(tr.m2), E._ptr(tr.grad), 1, 1e-3, E._stream())
+    got = tr.theta.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) < 1e-6
+    losses = [float(tr.step(xb, cg, 1e-3).item()) for _ in range(300)]
+    assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
