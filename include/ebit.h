@@ -181,6 +181,20 @@ int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, in
  * on theta with first / second moments m1, m2 (float32, param_count each). */
 int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t step, float lr, void *stream);
 
+/* Use the surrogate inside ebit_front2vof (theta: device parameters that stay
+ * valid while set; NULL switches back to the geometric construction only).
+ * Cells with a 4-marker face or more than one loop always use the geometric
+ * Front2VOF of sec. 2.5; the others take the network's output. */
+int ebit_set_surrogate(ebit_ctx *ctx, const float *theta);
+
+/* Training rows for the surrogate from the current state: for every
+ * unambiguous interfacial cell recomputed by the last ebit_front2vof (all of
+ * them when that call used a new C), its input row (bfloat16, 32 per row) and
+ * its geometric volume fraction (float32).  *count receives the number of
+ * rows; at most cap rows are written (x_bf16 / c may be NULL to only count).
+ * Rows are ordered by chunk (deterministic).  Synchronises stream. */
+int ebit_surrogate_dataset(ebit_ctx *ctx, void *x_bf16, float *c, int64_t cap, int64_t *count, void *stream);
+
 /* Free the context (not the caller's buffers). */
 void ebit_destroy(ebit_ctx *ctx);
 

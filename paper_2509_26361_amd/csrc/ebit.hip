@@ -35,6 +35,7 @@
 
 #include "../../include/ebit.h"
 #include "ebit_device.h"
+#include "mlp_device.h"
 
 using namespace ebit;
 
@@ -82,6 +83,8 @@ struct Work {
     uint32_t *ctask;     // per chunk kSeg interfacial cells
     uint32_t *ccnt;      // [nc]
     unsigned long long *cs;     // [CS_COUNT][nc] per-chunk counters
+    uint32_t *dcnt;      // [nc] surrogate-dataset rows per chunk
+    long long *doff;     // [nc] their offsets in the output
     unsigned long long *stat;   // ST_* totals
     double *part;        // 2 * kRedBlocks reduction partials
 };
@@ -109,6 +112,8 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(nc * kSeg * 4); if (w) w->ctask = (uint32_t *)p;
     p = take(nc * 4); if (w) w->ccnt = (uint32_t *)p;
     p = take(CS_COUNT * nc * 8); if (w) w->cs = (unsigned long long *)p;
+    p = take(nc * 4); if (w) w->dcnt = (uint32_t *)p;
+    p = take(nc * 8); if (w) w->doff = (long long *)p;
     p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
     p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
     return off;
@@ -893,6 +898,187 @@ __global__ __launch_bounds__(64) void k_f2v_b(F2VArgs<T> a)
     }
 }
 
+// Topology of a cell from flags alone (sec. 2.4): a face with four markers,
+// or face segments that close into more than one loop, make the cell
+// ambiguous (the surrogate's inputs do not determine its shape).
+__device__ __forceinline__ int cell_ambiguous(const uint8_t f[8], int has)
+{
+    int colb = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) colb |= (f[k] & 1) << k;
+    uint64_t lab = 0;
+#pragma unroll
+    for (int id = 0; id < 12; ++id) lab |= (uint64_t)id << (4 * id);
+#pragma unroll
+    for (int fc = 0; fc < 6; ++fc) {
+        int mk[4], ed[4], cnt = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            ed[m] = kTab.edge[fc][m];
+            mk[m] = (has >> ed[m]) & 1;
+            cnt += mk[m];
+        }
+        if (cnt == 4) return 1;
+        if (cnt == 2) {
+            int ia = -1, ib = -1;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (mk[m]) { if (ia < 0) ia = ed[m]; else ib = ed[m]; }
+            uint64_t la = (lab >> (4 * ia)) & 15, lb = (lab >> (4 * ib)) & 15;
+            if (la != lb) {
+                uint64_t keep = la < lb ? la : lb, drop = la < lb ? lb : la;
+#pragma unroll
+                for (int id = 0; id < 12; ++id)
+                    if (((lab >> (4 * id)) & 15) == drop) lab = (lab & ~(15ull << (4 * id))) | (keep << (4 * id));
+            }
+        }
+    }
+    int roots = 0;
+#pragma unroll
+    for (int id = 0; id < 12; ++id)
+        if (((has >> id) & 1) && ((lab >> (4 * id)) & 15) == (uint64_t)id) ++roots;
+    (void)colb;
+    return roots > 1;
+}
+
+// load an interfacial cell: corner flags, marker mask, fractions
+template <typename T>
+__device__ __forceinline__ int load_cell(const F2VArgs<T> &a, long q, uint8_t f[8], T sv[12])
+{
+    const int n = a.g.n;
+    const long nn = a.g.nn;
+    const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
+    long qc[8];
+    corner_flags(a.fl, n, nn, x, y, z, f, qc);
+    const int has = marker_mask(f);
+#pragma unroll
+    for (int id = 0; id < 12; ++id) {
+        int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
+        int cx = e == 0 ? 0 : oA, cy = e == 1 ? 0 : (e == 0 ? oA : oB), cz = e == 2 ? 0 : oB;
+        sv[id] = ((has >> id) & 1) ? a.s[e][qc[cx + 2 * cy + 4 * cz]] : T(0);
+    }
+    return has;
+}
+
+// surrogate input row of a cell: 12 fractions then 8 corner colours (bf16)
+template <typename T>
+__device__ __forceinline__ void put_features(__bf16 *row, const uint8_t f[8], const T sv[12])
+{
+#pragma unroll
+    for (int id = 0; id < 12; ++id) row[id] = ebit_mlp::to_bf16((float)sv[id]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) row[12 + k] = ebit_mlp::to_bf16((float)(f[k] & 1));
+#pragma unroll
+    for (int k = 20; k < ebit_mlp::kKIn; ++k) row[k] = ebit_mlp::to_bf16(0.f);
+}
+
+// Front2VOF phase B with the learned surrogate: unambiguous interfacial cells
+// take the network's volume fraction, computed on matrix cores 16 cells at a
+// time; ambiguous ones fall back to the geometric construction.  One wave per
+// chunk; the block's four waves share the weights in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *__restrict__ theta)
+{
+    using namespace ebit_mlp;
+    __shared__ MlpWeights W;
+    __shared__ __bf16 xs[4][64 * kRow1];
+    __shared__ __bf16 h1s[4][16 * kRow2];
+    __shared__ uint32_t rows[4][64];
+    load_weights(W, theta);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int nc = a.g.nc;
+    for (int ch = blockIdx.x * 4 + wave; ch < nc; ch += gridDim.x * 4) {
+        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
+        int ambc = 0;
+        for (uint32_t base = 0; base < count; base += 64) {
+            const uint32_t i = base + lane;
+            const bool valid = i < count;
+            long q = 0;
+            uint8_t f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            T sv[12];
+            int has = 0, amb = 0;
+            if (valid) {
+                q = (long)a.w.ctask[(size_t)ch * kSeg + i];
+                has = load_cell<T>(a, q, f, sv);
+                amb = cell_ambiguous(f, has);
+            }
+            if (valid && amb) {
+                int am = 0;
+                a.C[q] = cell_volume<T>(f, has, sv, am);
+                ambc += 1;
+            }
+            const bool sur = valid && !amb;
+            const unsigned long long bal = __ballot(sur);
+            const int nsur = __popcll(bal);
+            if (sur) {
+                const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+                put_features<T>(&xs[wave][pos * kRow1], f, sv);
+                rows[wave][pos] = (uint32_t)q;
+            }
+            wave_sync();
+            for (int t0 = 0; t0 < nsur; t0 += 16) {
+                const int rrow = t0 + lr;
+                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (rrow < nsur) v = *(const u16x8 *)&xs[wave][rrow * kRow1 + 8 * lg];
+                float out[4];
+                forward_tile(W, h1s[wave], __builtin_bit_cast(bf16x8, v), out, nullptr, nullptr);
+                if (lr == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = t0 + 4 * lg + r;
+                        if (rr < nsur) a.C[rows[wave][rr]] = (T)out[r];
+                    }
+                }
+            }
+            wave_sync();
+        }
+        const int sa = wave_sum(ambc);
+        if (lane == 0) a.w.cs[CS_AMB * nc + ch] = (unsigned long long)sa;
+    }
+}
+
+// Surrogate training rows: per chunk, the unambiguous interfacial cells of
+// the last Front2VOF (count pass, then write pass at host-computed offsets).
+template <typename T>
+__global__ __launch_bounds__(64) void k_dataset(F2VArgs<T> a, int write, uint16_t *__restrict__ xout,
+                                                float *__restrict__ cout, long cap)
+{
+    const int lane = threadIdx.x;
+    const int nc = a.g.nc;
+    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
+        long pos = write ? a.w.doff[ch] : 0;
+        for (uint32_t base = 0; base < count; base += 64) {
+            const uint32_t i = base + lane;
+            const bool valid = i < count;
+            uint8_t f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            T sv[12];
+            int has = 0, amb = 1;
+            if (valid) {
+                has = load_cell<T>(a, (long)a.w.ctask[(size_t)ch * kSeg + i], f, sv);
+                amb = cell_ambiguous(f, has);
+            }
+            const bool take = valid && !amb;
+            const unsigned long long bal = __ballot(take);
+            if (write && take) {
+                const long r = pos + __popcll(bal & ((1ull << lane) - 1ull));
+                if (r < cap) {
+                    __bf16 row[ebit_mlp::kKIn];
+                    put_features<T>(row, f, sv);
+#pragma unroll
+                    for (int k = 0; k < ebit_mlp::kKIn; ++k) xout[r * ebit_mlp::kKIn + k] = __builtin_bit_cast(uint16_t, row[k]);
+                    int am = 0;
+                    cout[r] = (float)cell_volume<T>(f, has, sv, am);
+                }
+            }
+            pos += __popcll(bal);
+        }
+        if (!write && lane == 0) a.w.dcnt[ch] = (uint32_t)pos;
+    }
+}
+
 // totals of the per-chunk counters (integer sums: order-free)
 __global__ __launch_bounds__(256) void k_stats_reduce(Work w, Geo g)
 {
@@ -1008,6 +1194,7 @@ struct ebit_ctx {
     uint32_t last_t_f2v;   // sweep counter at the last Front2VOF
     int full;              // process every brick
     const void *lastC;     // C array of the previous Front2VOF
+    const float *surr;     // surrogate parameters (NULL: geometric Front2VOF only)
     int grid_a;            // phase-A grid (64-lane workgroups)
     int grid_b;            // phase-B grid (256-lane blocks)
 };
@@ -1076,11 +1263,51 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     a.gen = c->fgen;
     a.full = full;
     hipLaunchKernelGGL((k_f2v_a<T>), dim3(clampi(c->g.nc, c->grid_a)), dim3(64), 0, st, a);
-    hipLaunchKernelGGL((k_f2v_b<T>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
+    if (c->surr)
+        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nc + 3) / 4, 256 * 2)), dim3(256), 0, st, a, c->surr);
+    else
+        hipLaunchKernelGGL((k_f2v_b<T>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
     c->fgen++;
     c->last_t_f2v = c->t;
     c->lastC = C;
     return check_launch();
+}
+
+template <typename T>
+int dataset_impl(ebit_ctx *c, void *x_bf16, float *cout, int64_t cap, int64_t *count, hipStream_t st)
+{
+    if (c->fgen < 2) return EBIT_EINVAL;                  // no Front2VOF yet
+    F2VArgs<T> a;
+    a.g = c->g;
+    a.fl = c->flags[c->cur];
+    for (int e = 0; e < 3; ++e) a.s[e] = (const T *)c->s[c->cur][e];
+    a.C = nullptr;
+    a.w = c->w;
+    a.gen = c->fgen - 1;
+    a.full = 0;
+    int grid = clampi(c->g.nc, c->grid_a);
+    hipLaunchKernelGGL((k_dataset<T>), dim3(grid), dim3(64), 0, st, a, 0, (uint16_t *)nullptr, (float *)nullptr, 0L);
+    if (check_launch() != EBIT_OK) return EBIT_EHIP;
+    const int nc = c->g.nc;
+    uint32_t *hc = (uint32_t *)malloc((size_t)nc * 4);
+    long long *ho = (long long *)malloc((size_t)nc * 8);
+    if (!hc || !ho) { free(hc); free(ho); return EBIT_EINVAL; }
+    int rc = EBIT_OK;
+    if (hipMemcpyAsync(hc, c->w.dcnt, (size_t)nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) rc = EBIT_EHIP;
+    long long tot = 0;
+    for (int k = 0; k < nc && rc == EBIT_OK; ++k) { ho[k] = tot; tot += hc[k]; }
+    if (rc == EBIT_OK && (hipMemcpyAsync(c->w.doff, ho, (size_t)nc * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+                          hipStreamSynchronize(st) != hipSuccess)) rc = EBIT_EHIP;
+    free(hc);
+    free(ho);
+    if (rc != EBIT_OK) return rc;
+    *count = tot;
+    if (x_bf16 && cout && cap > 0) {
+        hipLaunchKernelGGL((k_dataset<T>), dim3(grid), dim3(64), 0, st, a, 1, (uint16_t *)x_bf16, cout, (long)cap);
+        rc = check_launch();
+    }
+    return rc;
 }
 
 }  // namespace
@@ -1152,6 +1379,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->last_t_f2v = 0;
     c->full = 0;
     c->lastC = nullptr;
+    c->surr = nullptr;
     c->grid_a = 256 * 24;       // persistent: 24 single-wave workgroups per CU
     c->grid_b = 256 * 16;       // 16 single-wave workgroups per CU
     hipStream_t st = S(stream);
@@ -1244,6 +1472,20 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
 }
 
 int ebit_current(const ebit_ctx *c) { return c ? c->cur : -1; }
+
+int ebit_set_surrogate(ebit_ctx *c, const float *theta)
+{
+    if (!c) return EBIT_EINVAL;
+    c->surr = theta;
+    return EBIT_OK;
+}
+
+int ebit_surrogate_dataset(ebit_ctx *c, void *x_bf16, float *cout, int64_t cap, int64_t *count, void *stream)
+{
+    if (!c || !count || cap < 0) return EBIT_EINVAL;
+    if (c->precision == EBIT_FP64) return dataset_impl<double>(c, x_bf16, cout, cap, count, S(stream));
+    return dataset_impl<float>(c, x_bf16, cout, cap, count, S(stream));
+}
 
 int ebit_set_option(ebit_ctx *c, int option, int value)
 {

@@ -97,6 +97,10 @@ def lib():
         L.ebit_mlp_gradient.restype = ctypes.c_int
         L.ebit_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float, P]
         L.ebit_mlp_adam.restype = ctypes.c_int
+        L.ebit_set_surrogate.argtypes = [P, P]
+        L.ebit_set_surrogate.restype = ctypes.c_int
+        L.ebit_surrogate_dataset.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
+        L.ebit_surrogate_dataset.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -210,6 +214,28 @@ class Ebit:
         if rc not in (EBIT_OK, EBIT_ECFL) or (check_cfl and rc == EBIT_ECFL):
             raise EbitError(rc, "ebit_stats")
         return st.as_dict()
+
+    def set_surrogate(self, theta):
+        """Front2VOF uses the surrogate for unambiguous cells (None: off)."""
+        self._surr = theta
+        rc = lib().ebit_set_surrogate(self.ctx, _ptr(theta) if theta is not None else None)
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_set_surrogate")
+
+    def dataset(self, stream=None):
+        """(x_bf16 (m, 32), c (m,)) training rows of the last Front2VOF."""
+        cnt = ctypes.c_int64(0)
+        rc = lib().ebit_surrogate_dataset(self.ctx, None, None, 0, ctypes.byref(cnt), _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_surrogate_dataset")
+        m = cnt.value
+        x = torch.zeros((m, 32), dtype=torch.bfloat16, device=self.device)
+        c = torch.zeros(m, dtype=torch.float32, device=self.device)
+        if m:
+            rc = lib().ebit_surrogate_dataset(self.ctx, _ptr(x), _ptr(c), m, ctypes.byref(cnt), _stream(stream))
+            if rc != EBIT_OK:
+                raise EbitError(rc, "ebit_surrogate_dataset")
+        return x, c
 
     def _destroy(self):
         if self.ctx:
