@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# surrogate 20 -> 128 -> 128 -> 1: multiply-adds per row of the forward pass;
+# the gradient adds dW2, dh1 (128 x 128 each) and dW1 (20 x 128)
+MLP_FWD_FLOP = 2 * (20 * 128 + 128 * 128 + 128)
+MLP_GRAD_FLOP = MLP_FWD_FLOP + 2 * (2 * 128 * 128 + 20 * 128 + 128)
 # algorithmic bytes per interfacial cell (FP64 / FP32 storage):
 #   sweep: read s_x,s_y,s_z + flags + U_d, write s_x,s_y,s_z + flags
 #   Front2VOF: read s_x,s_y,s_z + flags, write C
@@ -45,11 +49,16 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true", help="skip the FP32 precision-form run")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-surrogate", action="store_true", help="skip training / running the learned Front2VOF")
+    p.add_argument("--surr-rows", type=int, default=2_000_000, help="training rows (unambiguous cells)")
+    p.add_argument("--surr-steps", type=int, default=20000, help="Adam steps")
+    p.add_argument("--surr-batch", type=int, default=8192)
     return p.parse_args()
 
 
-def run_case(E, I, torch, n, precision, W, K, events):
-    """W untimed steps, then K timed steps of the deformation workload."""
+def run_case(E, I, torch, n, precision, W, K, events, theta=None):
+    """W untimed steps, then K timed steps of the deformation workload
+    (Front2VOF through the learned surrogate when `theta` is given)."""
     T_end = 3.0
     dt = 0.5 / n
     dev = torch.device("cuda:0")
@@ -61,6 +70,8 @@ def run_case(E, I, torch, n, precision, W, K, events):
     e = E.Ebit(n, precision, dev)
     e.init(tdev(sh.phi_nodes), [tdev(f) for f in sh.phi_faces])
     del sh
+    if theta is not None:
+        e.set_surrogate(theta)
     C = torch.zeros((n, n, n), dtype=dtype, device=dev)
     e.front2vof(C)
     C0 = C.clone()
@@ -168,11 +179,12 @@ def main():
         "band_bricks_per_sweep": (st1["n_active_cells"] - st0["n_active_cells"]) / 64.0 / (3 * K),
     }
 
+    print(f"[bench] {a.precision}: {out['ms_per_step']:.3f} ms/step, {value:.3e} cells/s", file=sys.stderr, flush=True)
+    C64, V64 = r["C"], out["volume"]["end"]
+    del r
+    torch.cuda.empty_cache()
     if a.precision == "fp64" and not a.no_fp32:
         # precision form: same workload in FP32, errors against this FP64 run
-        C64, V64 = r["C"], out["volume"]["end"]
-        del r
-        torch.cuda.empty_cache()
         q = run_case(E, I, torch, n, "fp32", W, K, events=False)
         V32 = q["st1"]["volume"] + q["st1"]["volume_comp"]
         e32 = float((q["C"] - q["C0"]).abs().sum() / q["C0"].sum())
@@ -184,12 +196,100 @@ def main():
             "e_shape_at_T": e32 if q["ended_at_T"] else None,
             "e_shape_ratio_fp32_over_fp64": (e32 / e_shape) if (q["ended_at_T"] and e_shape > 0) else None,
         }
+        print(f"[bench] fp32 form done: {out['fp32_form']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         del q
+        torch.cuda.empty_cache()
+
+    if a.precision == "fp64" and not a.no_surrogate:
+        out["fp32_surrogate_form"] = surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape)
         torch.cuda.empty_cache()
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
+    """Learned Front2VOF: training rows from the method's own FP64 runs of
+    seeded ellipsoids at 128^3, training on the GPU (bf16 matrix cores), then
+    the FP32 form with the surrogate on the same workload, against FP64."""
+    from paper_2509_26361_amd import surrogate as SG
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    calls = [0]
+
+    def log(msg):
+        calls[0] += 1
+        if calls[0] % 50 == 1:
+            print(f"[bench] surrogate rows: {msg}", file=sys.stderr, flush=True)
+    X, c = SG.make_dataset(n=128, shapes=100000, snapshots=6, seed=0, device=dev, max_rows=a.surr_rows, log=log)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    m = X.shape[0]
+    nval = max(1, m // 20)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    perm = torch.randperm(m, generator=g).to(dev)
+    Xv, cv = X[perm[:nval]], c[perm[:nval]]
+    Xt, ct = X[perm[nval:]], c[perm[nval:]]
+    del X, c, perm
+    theta = torch.from_numpy(I.mlp_init(0).astype(np.float32)).to(dev)
+    mae0, _ = SG.evaluate(theta, Xv, cv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta = SG.train(Xt, ct, steps=a.surr_steps, batch=a.surr_batch, lr=2e-3, seed=0, theta=theta,
+                     log=lambda msg: print(f"[bench] surrogate {msg}", file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    mae, mx = SG.evaluate(theta, Xv, cv)
+    bias = float((E.mlp_forward(theta, Xv) - cv).mean().item())
+    # gradient kernel alone, timed with HIP events on its stream
+    tr = E.MlpTrainer(theta.clone(), dev)
+    xb, cb = Xt[:a.surr_batch].contiguous(), ct[:a.surr_batch].contiguous()
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        tr.gradient(xb, cb)
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record(stream)
+    reps = 50
+    for _ in range(reps):
+        tr.gradient(xb, cb)
+    e_ev.record(stream)
+    torch.cuda.synchronize()
+    grad_s = s_ev.elapsed_time(e_ev) * 1e-3 / reps
+    fwd_rows = Xv
+    s_ev.record(stream)
+    for _ in range(reps):
+        E.mlp_forward(theta, fwd_rows)
+    e_ev.record(stream)
+    torch.cuda.synchronize()
+    fwd_s = s_ev.elapsed_time(e_ev) * 1e-3 / reps
+    del Xt, ct, tr
+    torch.cuda.empty_cache()
+    q = run_case(E, I, torch, n, "fp32", W, K, events=True, theta=theta)
+    V = q["st1"]["volume"] + q["st1"]["volume_comp"]
+    es = float((q["C"] - q["C0"]).abs().sum() / q["C0"].sum())
+    tot = {k: sum(v) for k, v in q["kt"].items()}
+    return {
+        "value": q["n_start"] / q["wall"],
+        "ms_per_step": q["wall"] / K * 1e3,
+        "f2v_ms_per_call": tot["f2v"] / K * 1e3,
+        "volume_rel_err_vs_fp64": abs(V - V64) / V64,
+        "max_abs_C_diff_vs_fp64": float((q["C"] - C64).abs().max()),
+        "e_shape_at_T": es if q["ended_at_T"] else None,
+        "e_shape_ratio_over_fp64": (es / e_shape64) if (q["ended_at_T"] and e_shape64) else None,
+        "ambiguous_cells_end": q["st1"]["n_ambiguous"],
+        "interfacial_cells_end": q["st1"]["n_interfacial"],
+        "training": {
+            "rows": m, "holdout_rows": nval, "dataset_s": t_data, "train_s": t_train,
+            "steps": a.surr_steps, "batch": a.surr_batch,
+            "holdout_mae": mae, "holdout_max_err": mx, "holdout_bias": bias, "untrained_mae": mae0,
+            "gradient_us": grad_s * 1e6,
+            "gradient_tflops": MLP_GRAD_FLOP * a.surr_batch / grad_s / 1e12,
+            "forward_rows_per_s": nval / fwd_s,
+            "forward_tflops": MLP_FWD_FLOP * nval / fwd_s / 1e12,
+            "bf16_mfma_peak_tflops": 2500.0,
+        },
+    }
 
 
 def cpu_baseline(n, budget_s):
