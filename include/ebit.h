@@ -6,7 +6,8 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * Grid: n^3 cells of size h = 1/n, periodic, n a multiple of 4 and >= 8.
+ * Grid: n^3 cells of size h = 1/n, periodic, n a multiple of 4, 8 <= n <= 1024
+ * (node indices fit 32 bits).
  * Node (i,j,k) has linear index i + n*(j + n*k) (x fastest); every array
  * below has n^3 entries in that order.
  *
@@ -143,9 +144,38 @@ int ebit_stats(ebit_ctx *ctx, const void *C, ebit_stats_t *out, void *stream);
 /* Index (0 or 1) of the state buffer holding the current state. */
 int ebit_current(const ebit_ctx *ctx);
 
+/*
+ * `nsteps` steps of the hot path, launched from the library: per step k the
+ * sweeps along x, y and z (ebit_advect_sweep with time factor g[k] and step
+ * dt, the time level of the step for all three, sec. 2.3), then Front2VOF
+ * into C (ebit_front2vof) unless C is NULL.
+ *   U       3 device pointers: U_x, U_y, U_z (n^3 each, the precision's type)
+ *   g       host array of nsteps time factors
+ * Returns the first error of the calls it makes (the steps before it are
+ * enqueued).
+ */
+int ebit_advance(ebit_ctx *ctx, int32_t nsteps, const void *const *U, const double *g, double dt, void *C,
+                 void *stream);
+
 /* Option switches. */
-enum { EBIT_OPT_FULL_GRID = 1 };   /* 1: process every cell, not only the band */
+enum {
+    EBIT_OPT_FULL_GRID = 1,   /* 1: process every cell, not only the band */
+    EBIT_OPT_TIMING = 2       /* 1: bracket each sweep / Front2VOF launch with HIP events on its stream */
+};
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
+
+/* Launch times recorded while EBIT_OPT_TIMING is on (at most 8192 launches
+ * between two calls; later ones are not timed). */
+typedef struct {
+    int64_t sweeps;         /* timed ebit_advect_sweep launches */
+    double sweep_ms;        /* their summed duration */
+    int64_t f2v;            /* timed Front2VOF launches (the surrogate's included) */
+    double f2v_ms;
+} ebit_timing_t;
+
+/* Read and reset the accumulated launch times.  Synchronises with the last
+ * timed launch. */
+int ebit_timing(ebit_ctx *ctx, ebit_timing_t *out);
 
 /* ------------------------------------------------------------------------ *
  * Learned Front2VOF surrogate (not part of the paper): a multilayer

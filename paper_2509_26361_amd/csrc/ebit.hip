@@ -3,29 +3,29 @@
 // advection sweep and Front2VOF (Pan et al., arXiv 2509.26361, secs. 2.1-2.5,
 // 3.1), plus a deterministic compensated volume reduction.
 //
-// Band.  Work is restricted to 4x4x4-node bricks near the interface.  A sweep
-// processes a brick when it is, or neighbours (26-neighbourhood), a brick that
-// held a marker before this sweep or before the previous one: markers move at
-// most one cell per sweep and every output depends only on markers within
-// three cells, so outside the band the state is constant and the result
-// equals a full-grid sweep.  Activity is kept as per-brick stamps (the sweep
-// number at which a brick entered the band), so no list and no shared counter
-// is needed: each sweep stamps the bricks of the next one.
+// Band.  Work is restricted to 4x4x4-node bricks near the interface.  Sweep t
+// processes the bricks next to (26-neighbourhood) a brick that held a marker
+// before sweep t or before sweep t-1: markers move at most one cell per sweep
+// and every output depends only on markers within three cells, so outside the
+// band the state is constant and the result equals a full-grid sweep (the
+// second condition keeps both state buffers equal outside the band).
 //
-// Chunks.  Bricks are grouped in chunks of 64 (brick c + k * nchunks, k <
-// 64), scattered over the grid.  A workgroup owns a chunk while processing
-// it: it writes the chunk's task segments, task counts and counters with
-// plain stores, so the hot kernels issue no same-address atomics (those are
-// serialised at memory across the XCDs of the chip).
+// Lists.  Each sweep builds the band list of the next one: a brick holding a
+// marker claims its 27 neighbours (an atomic exchange of a per-brick stamp
+// decides the one claimant) and appends the new ones, wave-aggregated, to one
+// of kSub sub-lists with a counter each (sub-list = wave id mod kSub), so no
+// single address takes every append.  The same scheme builds the list of
+// bricks that the next Front2VOF must revisit.
 //
-// Sweep = two kernels.  Phase A (one 64-lane workgroup per chunk, one lane per
-// node of the current brick, the brick and a one-node halo staged in LDS):
-// new node colours, aligned markers, which edges carry a marker afterwards,
-// colours of faces with uniform corners, and the task segments -- the nodes
-// whose new unaligned marker must be placed by the circle fit and the faces
-// whose corners differ.  Phase B (256-lane blocks over chunks): the tasks,
-// one per lane, densely.  Front2VOF is split the same way: full/empty cells
-// first, then one interfacial cell per lane.
+// Waves.  Both kernels run one 64-lane wave per workgroup over a fixed grid
+// of nw waves; wave w takes list items w, w + nw, ... (balanced to one brick).
+// A sweep wave stages each brick and a halo in LDS (one lane per node), writes
+// the new colours, aligned markers and uniform face colours, and queues the
+// work that needs the neighbourhood (new unaligned markers, colours of faces
+// whose corners differ) in LDS; the queue is then run densely, one task per
+// lane, by one code path for both planes (the plane axis is a run-time value).
+// Front2VOF waves classify each brick's cells (full, empty, interfacial) and
+// queue the interfacial ones, whose volumes are then computed one per lane.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -39,19 +39,34 @@
 
 using namespace ebit;
 
+// occupancy targets (waves per SIMD) of the sweep and Front2VOF kernels
+#ifndef EBIT_SWEEP_WAVES
+#define EBIT_SWEEP_WAVES 3
+#endif
+#ifndef EBIT_F2V_WAVES
+#define EBIT_F2V_WAVES 3
+#endif
+
 namespace {
 
 constexpr int kRedBlocks = 1024;
-constexpr int kChunk = 64;              // bricks per chunk
-constexpr int kSeg = kChunk * 64;       // task segment length per chunk (one per node)
+constexpr int kSub = 16;          // sub-lists per brick list
+#ifndef EBIT_MAX_WAVES
+#define EBIT_MAX_WAVES 3072
+#endif
+constexpr int kMaxWaves = EBIT_MAX_WAVES;   // waves of the sweep / Front2VOF grids
+constexpr int kTaskCap = 512;     // sweep: queued tasks per wave
+constexpr int kSlotCap = 128;     // sweep: queued face nodes per wave
+constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
+constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
 
-// totals reduced from the per-chunk counters
+// totals reduced from the per-wave counters
 enum {
     ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB,
     ST_MARK0, ST_MARK1, ST_MARK2, ST_COUNT = 16
 };
-// per-chunk counters: cumulative over sweeps / Front2VOF calls, except the
-// last-Front2VOF ones
+// per-wave counters: cumulative over sweeps / Front2VOF calls, except the
+// last-Front2VOF one (CS_AMB)
 enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_SUM, CS_INTER, CS_AMB, CS_COUNT };
 
 struct Geo {
@@ -59,61 +74,63 @@ struct Geo {
     int nb1;        // bricks per axis
     long nn;        // n*n
     int nb;         // bricks
-    int nc;         // chunks
-    long hmul;      // brick of chunk slot j: (j * hmul) mod nb, hmul coprime with nb
+    int nw;         // waves of the sweep / Front2VOF grids
+    long segcap;    // interfacial-cell segment length per wave
 };
 
-// Chunk ch holds slots 64 ch .. 64 ch + 63; slot j is brick (j * hmul) mod nb,
-// a permutation that scatters a chunk's bricks over the grid (balanced work
-// per chunk, no same-address contention between chunks).
-__device__ __forceinline__ int chunk_brick(const Geo &g, int ch, int k, bool &valid)
+int waves_for(int n)
 {
-    long j = (long)ch * 64 + k;
-    valid = j < g.nb;
-    return valid ? (int)((j * g.hmul) % g.nb) : 0;
+    const long nb = (long)(n / 4) * (n / 4) * (n / 4);
+    return (int)(nb < 64 ? 64 : (nb > kMaxWaves ? kMaxWaves : nb));
+}
+
+long segcap_for(int n)
+{
+    const long nb = (long)(n / 4) * (n / 4) * (n / 4);
+    const long nw = waves_for(n);
+    return ((nb + nw - 1) / nw) * 64;
 }
 
 // device work space carved out of the caller's scratch buffer
 struct Work {
-    uint32_t *cm[3];     // cm[t % 3][b] == t <=> brick b is next to a marker-holding brick before sweep t
-    uint32_t *fmark;     // fmark[b] == g <=> brick b must be revisited by Front2VOF generation g
+    uint32_t *cm[3];     // cm[t % 3][b] == t <=> brick b is in the band list of sweep t
+    uint32_t *fmark;     // fmark[b] == g <=> brick b is in the revisit list of Front2VOF generation g
     uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
-    uint32_t *task[4];   // per chunk kSeg node indices: unaligned fit (plane 1, 2), face colour (plane 1, 2)
-    uint32_t *tcnt;      // [4][nc] task counts
-    uint32_t *ctask;     // per chunk kSeg interfacial cells
-    uint32_t *ccnt;      // [nc]
-    unsigned long long *cs;     // [CS_COUNT][nc] per-chunk counters
-    uint32_t *dcnt;      // [nc] surrogate-dataset rows per chunk
-    long long *doff;     // [nc] their offsets in the output
+    uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of nb entries
+    uint32_t *bnum;      // [4][kSub] sub-list lengths
+    uint32_t *flist[2];  // revisit list of generation g: flist[g % 2]
+    uint32_t *fnum;      // [2][kSub]
+    uint32_t *ctask;     // per wave segcap interfacial cells of the last Front2VOF
+    uint32_t *ccnt;      // [nw] their counts
+    unsigned long long *cs;     // [CS_COUNT][nw] per-wave counters
+    uint32_t *dcnt;      // [nw] surrogate-dataset rows per wave
+    long long *doff;     // [nw] their offsets in the output
     unsigned long long *stat;   // ST_* totals
     double *part;        // 2 * kRedBlocks reduction partials
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int chunks_for(int n)
-{
-    long nb = (long)(n / 4) * (n / 4) * (n / 4);
-    return (int)((nb + kChunk - 1) / kChunk);
-}
-
 size_t work_layout(int n, Work *w, char *base)
 {
-    size_t nb = (size_t)(n / 4) * (n / 4) * (n / 4);
-    size_t nc = (size_t)chunks_for(n);
+    const size_t nb = (size_t)(n / 4) * (n / 4) * (n / 4);
+    const size_t nw = (size_t)waves_for(n);
+    const size_t seg = (size_t)segcap_for(n);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return base ? base + o : nullptr; };
     char *p;
     for (int k = 0; k < 3; ++k) { p = take(nb * 4); if (w) w->cm[k] = (uint32_t *)p; }
     p = take(nb * 4); if (w) w->fmark = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bcnt = (uint32_t *)p;
-    for (int k = 0; k < 4; ++k) { p = take(nc * kSeg * 4); if (w) w->task[k] = (uint32_t *)p; }
-    p = take(4 * nc * 4); if (w) w->tcnt = (uint32_t *)p;
-    p = take(nc * kSeg * 4); if (w) w->ctask = (uint32_t *)p;
-    p = take(nc * 4); if (w) w->ccnt = (uint32_t *)p;
-    p = take(CS_COUNT * nc * 8); if (w) w->cs = (unsigned long long *)p;
-    p = take(nc * 4); if (w) w->dcnt = (uint32_t *)p;
-    p = take(nc * 8); if (w) w->doff = (long long *)p;
+    for (int k = 0; k < 4; ++k) { p = take(kSub * nb * 4); if (w) w->blist[k] = (uint32_t *)p; }
+    p = take(4 * kSub * 4); if (w) w->bnum = (uint32_t *)p;
+    for (int k = 0; k < 2; ++k) { p = take(kSub * nb * 4); if (w) w->flist[k] = (uint32_t *)p; }
+    p = take(2 * kSub * 4); if (w) w->fnum = (uint32_t *)p;
+    p = take(nw * seg * 4); if (w) w->ctask = (uint32_t *)p;
+    p = take(nw * 4); if (w) w->ccnt = (uint32_t *)p;
+    p = take(CS_COUNT * nw * 8); if (w) w->cs = (unsigned long long *)p;
+    p = take(nw * 4); if (w) w->dcnt = (uint32_t *)p;
+    p = take(nw * 8); if (w) w->doff = (long long *)p;
     p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
     p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
     return off;
@@ -133,15 +150,99 @@ __device__ __forceinline__ int wave_sum(int v)
     return v;
 }
 
-// Wave-aggregated write of the lanes' entries at seg[pos...]; `pos` is the
-// wave-uniform fill level.
-__device__ __forceinline__ void wave_put(uint32_t *seg, int &pos, bool take, uint32_t val)
+// inclusive prefix sum over the lanes of the wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    unsigned long long bal = __ballot(take);
-    int lane = threadIdx.x & 63;
-    if (take) seg[pos + __popcll(bal & ((1ull << lane) - 1ull))] = val;
-    pos += __popcll(bal);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    return v;
 }
+
+// Claims of list membership, batched per wave: the bricks at offsets
+// `per` = 27 (the 3x3x3 neighbourhood) or 8 (the brick and its lower
+// neighbours) of `nsrc` source bricks join the list whose membership is
+// `mark[b] == v`.  An atomic exchange of the mark decides the one claimant of
+// each brick, which appends it, wave-aggregated, to sub-list `sub`.  Four
+// claims per lane are in flight at a time.
+__device__ __forceinline__ void claim_batch(const int *src, int nsrc, int per, int nb1, uint32_t *mark, uint32_t v,
+                                            uint32_t *list, uint32_t *num, int sub, uint32_t cap)
+{
+    const int lane = threadIdx.x & 63;
+    const int total = nsrc * per;
+    for (int base = 0; base < total; base += 256) {
+        int nbk[4];
+        bool take[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = base + 64 * u + lane;
+            take[u] = false;
+            nbk[u] = 0;
+            if (c < total) {
+                const int b = src[c / per], d = c % per;
+                nbk[u] = per == 27 ? brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1)
+                                   : brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + 64 * u + lane < total) take[u] = atomicExch(&mark[nbk[u]], v) != v;
+        unsigned long long bal[4];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { bal[u] = __ballot(take[u]); cnt += __popcll(bal[u]); }
+        if (cnt == 0) continue;
+        uint32_t pos = 0;
+        if (lane == 0) pos = atomicAdd(&num[sub], (uint32_t)cnt);
+        pos = __shfl(pos, 0);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t p = pos + (uint32_t)__popcll(bal[u] & lt);
+            if (take[u] && p < cap) list[(size_t)sub * cap + p] = (uint32_t)nbk[u];
+            pos += (uint32_t)__popcll(bal[u]);
+        }
+    }
+}
+
+// Items of a grid: the concatenation of up to two lists of kSub sub-lists
+// (lane j < 2 kSub holds the length and inclusive prefix of sub-list j).
+struct Items {
+    uint32_t len, incl, total, nfirst;
+    const uint32_t *l0, *l1;
+    uint32_t cap;
+    __device__ __forceinline__ void init(const uint32_t *num0, const uint32_t *num1, const uint32_t *list0,
+                                         const uint32_t *list1, uint32_t nb)
+    {
+        const int lane = threadIdx.x & 63;
+        len = 0;
+        if (lane < kSub) len = min(num0[lane], nb);
+        else if (num1 && lane < 2 * kSub) len = min(num1[lane - kSub], nb);
+        incl = wave_incl_scan(len);
+        total = __shfl(incl, 63);
+        nfirst = __shfl(incl, kSub - 1);
+        l0 = list0;
+        l1 = list1;
+        cap = nb;
+    }
+    // brick of item k < total, a different k per lane (every lane must call)
+    __device__ __forceinline__ int brick_lane(uint32_t k) const
+    {
+        int j = 0;
+        uint32_t excl = 0;
+#pragma unroll
+        for (int m = 0; m < 2 * kSub; ++m) {
+            const uint32_t im = __shfl(incl, m);
+            if (im <= k) { j = m + 1; excl = im; }
+        }
+        if (j >= 2 * kSub) return -1;
+        const uint32_t *l = j < kSub ? l0 : l1;
+        return (int)l[(size_t)(j % kSub) * cap + (k - excl)];
+    }
+};
 
 // ---------------------------------------------------------------------------
 // a0: initialisation (sec. 3.1)
@@ -196,8 +297,8 @@ __global__ __launch_bounds__(256) void k_init(Geo g, const double *__restrict__ 
     fl[q] = out;
 }
 
-// Stamps of a freshly initialised (or caller-filled) state: the first sweep
-// (t = 2; stamps start at 0) processes the bricks next to a brick holding a
+// Band list of the first sweep (t = 2; stamps start at 0) of a freshly
+// initialised (or caller-filled) state: the bricks next to a brick holding a
 // marker.
 __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restrict__ fl, Work w)
 {
@@ -206,12 +307,12 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         int bx = b % g.nb1, by = (b / g.nb1) % g.nb1, bz = b / (g.nb1 * g.nb1);
         int x = bx * 4 + (lane & 3), y = by * 4 + ((lane >> 2) & 3), z = bz * 4 + (lane >> 4);
         long q = x + (long)g.n * y + g.nn * z;
-        bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
-        if (hasm && lane < 27) w.cm[2][brick_shift(b, g.nb1, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1)] = 2u;
+        const bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
+        if (hasm) claim_batch(&b, 1, 27, g.nb1, w.cm[2], 2u, w.blist[2], w.bnum + 2 * kSub, blockIdx.x % kSub, (uint32_t)g.nb);
     }
 }
 
-// zero the stamps and counters
+// zero the stamps, list lengths and counters
 __global__ void k_zero_work(Work w, Geo g)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,10 +323,11 @@ __global__ void k_zero_work(Work w, Geo g)
         w.fmark[i] = 0;
         w.bcnt[i] = 0;
     }
-    if (i < g.nc) {
-        for (int k = 0; k < 4; ++k) w.tcnt[k * g.nc + i] = 0;
+    if (i < 4 * kSub) w.bnum[i] = 0;
+    if (i < 2 * kSub) w.fnum[i] = 0;
+    if (i < g.nw) {
         w.ccnt[i] = 0;
-        for (int k = 0; k < CS_COUNT; ++k) w.cs[k * g.nc + i] = 0;
+        for (int k = 0; k < CS_COUNT; ++k) w.cs[k * g.nw + i] = 0;
     }
     if (i < ST_COUNT) w.stat[i] = 0;
 }
@@ -249,29 +351,89 @@ struct SweepArgs {
     int full;         // process every brick
 };
 
-// Phase A tile: flags and advected coordinate of the D-edge markers of the
+// Brick tile: flags and advected coordinate of the D-edge markers of the
 // brick's nodes and their neighbours at offsets -1..+1 along D and +1 across,
 // indexed iD + kAD (i1 + kAA i2), (iD, i1, i2) = offsets (+1, 0, 0) along (D, A1, A2).
 constexpr int kAD = 6, kAA = 5, kATile = kAD * kAA * kAA;
 
-// Phase A of a sweep, one 64-lane workgroup per chunk, its active bricks one
-// after the other: new node colours (one flip per aligned marker crossing a
+// The queued tasks of a sweep wave, one per lane: the circle-fit placement of
+// a new unaligned marker (type bit 1 clear) or the colour of a face whose
+// corners differ (bit 1 set) in the plane (D, A1) (bit 0 clear) or (D, A2);
+// bit 2 is the node's new colour.  Face colours are gathered per node in the
+// slot table and the node's flags byte is written once.
+template <typename T, int D>
+__device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t *tq, const uint8_t *tt,
+                                          const uint8_t *ts, int ntask, const uint32_t *sq, uint32_t *sb,
+                                          int nslot, int &fbt, int &multit)
+{
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    const int lane = threadIdx.x;
+    const int n = a.g.n;
+    const long nn = a.g.nn;
+    const long str[3] = {1, (long)n, nn};
+    for (int base = 0; base < ntask; base += 64) {
+        const int i = base + lane;
+        if (i < ntask) {
+            const long q = tq[i];
+            const int ty = tt[i];
+            const bool second = ty & 1;             // plane (D, A2)
+            const int face = (ty >> 1) & 1, c00 = (ty >> 2) & 1;
+            const int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / nn)};
+            PlaneTask<T, D> p;
+            p.fl = a.fl;
+            p.sD = a.s[D];
+            p.sA = second ? a.s[A2] : a.s[A1];
+            p.U = a.U;
+            p.c = a.c;
+            p.n = n;
+            p.ci = P[D];
+            p.cj = second ? P[A2] : P[A1];
+            p.strD = str[D];
+            p.strA = second ? str[A2] : str[A1];
+            p.base = second ? (long)P[A1] * str[A1] : (long)P[A2] * str[A2];
+            p.hb = 4 + D;
+            p.vb = second ? 4 + A2 : 4 + A1;
+            p.fb = second ? 1 + A1 : 1 + A2;
+            p.fetch_flags();
+            const T v = p.run(face, c00, fbt, multit);
+            if (!face) (second ? a.so[A2] : a.so[A1])[q] = v;
+            else if (v != T(0)) atomicOr(&sb[ts[i]], 1u << p.fb);
+        }
+    }
+    __syncthreads();
+    for (int s = lane; s < nslot; s += 64) a.flo[sq[s]] = (uint8_t)sb[s];
+    __syncthreads();
+}
+
+// One sweep: wave w takes the items w, w + nw, ... of the band lists of this
+// sweep and the previous one (a brick in both is taken once).  Per brick, one
+// lane per node: new node colours (one flip per aligned marker crossing a
 // node, Fig. 4), the aligned markers (land on the edge they reach, pairs
 // annihilate, Fig. 5a), which edges carry a marker afterwards (one marker iff
 // the end colours differ, sec. 2.2), the colour of faces with uniform
-// corners, and the chunk's task segments for phase B.  Stamps the bricks of
-// the next sweep and those Front2VOF must revisit.
+// corners; the rest is queued.  The bricks next to a brick holding markers
+// join the next sweep's list; bricks whose cells change join the next
+// Front2VOF's list.
 template <typename T, int D>
-__global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
+__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     __shared__ uint8_t tfl[kATile];
     __shared__ double txd[kATile];
+    __shared__ uint32_t tq[kTaskCap];
+    __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
+    __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
+    __shared__ int mbr[kClaimCap], cbr[kClaimCap];
     const int lane = threadIdx.x;
-    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb, nc = a.g.nc;
+    const int wv = blockIdx.x, nw = gridDim.x;
+    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const uint32_t t = a.t;
-    const uint32_t *cm_cur = a.w.cm[t % 3], *cm_prev = a.w.cm[(t + 2) % 3];
+    const uint32_t *cm_cur = a.w.cm[t % 3];
     uint32_t *cm_next = a.w.cm[(t + 1) % 3];
+    const int sub = wv % kSub;
+    uint32_t *lnext = a.w.blist[(t + 1) % 4], *nnext = a.w.bnum + ((t + 1) % 4) * kSub;
+    uint32_t *lrev = a.w.flist[a.fgen % 2], *nrev = a.w.fnum + (a.fgen % 2) * kSub;
+    if (wv == 0 && lane < kSub) a.w.bnum[((t + 2) % 4) * kSub + lane] = 0;   // sweep t+2's list starts empty
     const long str[3] = {1, (long)n, a.g.nn};
     const int lu[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
     const int tself = (lu[D] + 1) + kAD * (lu[A1] + kAA * lu[A2]);
@@ -279,40 +441,74 @@ __global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
     ext[D] = kAD; ext[A1] = kAA; ext[A2] = kAA;
     lo[D] = -1; lo[A1] = 0; lo[A2] = 0;
 
-    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
-        bool valid;
-        const int bl = chunk_brick(a.g, ch, lane, valid);
-        const bool act = valid && (a.full || cm_cur[bl] == t || cm_prev[bl] == t - 1);
-        unsigned long long pending = __ballot(act);
-        int nt[4] = {0, 0, 0, 0};
-        int fbc = 0, cflc = 0, mergedc = 0;
-        const int nact = __popcll(pending);
-        while (pending) {
-            const int k = __ffsll((long long)pending) - 1;
-            pending &= pending - 1;
-            const int b = __shfl(bl, k);
+    Items it;
+    if (a.full) {
+        it.total = (uint32_t)nb;
+        it.nfirst = (uint32_t)nb;
+    } else {
+        it.init(a.w.bnum + (t % 4) * kSub, a.w.bnum + ((t + 3) % 4) * kSub, a.w.blist[t % 4],
+                a.w.blist[(t + 3) % 4], (uint32_t)nb);
+    }
+    int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0;
+    int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
+    auto claims = [&]() {
+        __syncthreads();
+        claim_batch(mbr, nm, 27, nb1, cm_next, t + 1, lnext, nnext, sub, (uint32_t)nb);
+        claim_batch(cbr, nc, 8, nb1, a.w.fmark, a.fgen, lrev, nrev, sub, (uint32_t)nb);
+        __syncthreads();
+        nm = 0;
+        nc = 0;
+    };
+    // this wave's items k = wv + i nw, resolved 64 at a time (one per lane)
+    const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
+    for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
+        int bl = -1;
+        {
+            const uint32_t i = i0 + (uint32_t)lane;
+            const uint32_t k = (uint32_t)wv + i * (uint32_t)nw;
+            const bool have = i < mine;
+            int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
+            if (!have || bb < 0 || bb >= nb) bb = -1;
+            if (bb >= 0 && !a.full && k >= it.nfirst && cm_cur[bb] == t) bb = -1;   // also in this sweep's own list
+            bl = bb;
+        }
+        unsigned long long pend = __ballot(bl >= 0);
+        while (pend) {
+            const int src = __ffsll((long long)pend) - 1;
+            pend &= pend - 1;
+            const int b = __shfl(bl, src);
+            if (ntask + 4 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
+                run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
+                ntask = 0;
+                nslot = 0;
+            }
+            if (nm == kClaimCap || nc == kClaimCap) claims();
+            ++nact;
             const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+            const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
             int cfl = 0;
             // stage flags and the Euler step (eq. Eq_marker_dis) of D-edge markers;
-            // all flag loads first, then all marker loads
+            // all flag loads first, then all marker loads (with those of the
+            // unaligned markers stored at the lane's own node, for the Courant check)
+            const uint8_t fown = a.fl[qs];
             constexpr int kR = (kATile + 63) / 64;
             long qr[kR];
             uint8_t fr[kR];
             int gpd[kR];
-#pragma unroll
+    #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 int kk = lane + 64 * r;
                 int kc = kk < kATile ? kk : kATile - 1;
                 int kt[3] = {kc % ext[0], (kc / ext[0]) % ext[1], kc / (ext[0] * ext[1])};
                 int gp[3];
-#pragma unroll
+    #pragma unroll
                 for (int e = 0; e < 3; ++e) gp[e] = wrp(org[e] + lo[e] + kt[e], n);
                 qr[r] = gp[0] + str[1] * gp[1] + str[2] * gp[2];
                 gpd[r] = gp[D];
                 fr[r] = a.fl[qr[r]];
             }
             T sD[kR], U0[kR], UD[kR];
-#pragma unroll
+    #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 sD[r] = U0[r] = UD[r] = T(0);
                 if ((fr[r] >> (4 + D)) & 1) {
@@ -322,7 +518,19 @@ __global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
                     UD[r] = a.U[gpd[r] + 1 == n ? q - (long)(n - 1) * str[D] : q + str[D]];
                 }
             }
-#pragma unroll
+            T sAo[2], UAo[2], Uown = T(0);
+            if (fown & ((1u << (4 + A1)) | (1u << (4 + A2)))) Uown = a.U[qs];
+    #pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int A = e == 0 ? A1 : A2;
+                sAo[e] = UAo[e] = T(0);
+                if ((fown >> (4 + A)) & 1) {
+                    const long q1 = org[A] + lu[A] + 1 == n ? qs - (long)(n - 1) * str[A] : qs + str[A];
+                    sAo[e] = a.s[A][qs];
+                    UAo[e] = a.U[q1];
+                }
+            }
+    #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 int kk = lane + 64 * r;
                 if (kk >= kATile) continue;
@@ -352,7 +560,6 @@ __global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
             __syncthreads();
             auto ncol = [&](int di, int d1, int d2) { return (tfl[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
             const uint8_t fself = tfl[tself];
-            const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
             const int c00 = ncol(0, 0, 0), c10 = ncol(1, 0, 0);
             uint8_t out = (uint8_t)c00;
             T sdn = T(0);
@@ -383,14 +590,11 @@ __global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
             }
             out |= (uint8_t)(fself & (1u << (1 + D)));   // faces normal to D keep their colour
             // Courant check of the unaligned markers stored at this node
-#pragma unroll
+    #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int A = e == 0 ? A1 : A2;
-                if ((fself >> (4 + A)) & 1) {
-                    long q1 = org[A] + lu[A] + 1 == n ? qs - (long)(n - 1) * str[A] : qs + str[A];
-                    T s = a.s[A][qs];
-                    T U0s = a.U[qs];
-                    T del = a.c * (U0s + s * (a.U[q1] - U0s));
+                if ((fown >> (4 + A)) & 1) {
+                    T del = a.c * (Uown + sAo[e] * (UAo[e] - Uown));
                     if (fabs((double)del) > 1.0) ++cfl;
                 }
             }
@@ -409,140 +613,63 @@ __global__ __launch_bounds__(64) void k_sweep_a(SweepArgs<T> a)
                 if (task[1]) out |= (uint8_t)(1u << (4 + A2));
                 if (!task[3]) out |= (uint8_t)(c00 << (1 + A1));
             }
-            a.flo[qs] = out;
             a.so[D][qs] = sdn;
             if (!task[0]) a.so[A1][qs] = T(0);
             if (!task[1]) a.so[A2][qs] = T(0);
-#pragma unroll
-            for (int kt = 0; kt < 4; ++kt) wave_put(a.w.task[kt] + (size_t)ch * kSeg, nt[kt], task[kt], (uint32_t)qs);
-
-            // stamps: the next sweep takes the bricks next to a brick holding
-            // markers now (and this sweep's core); Front2VOF revisits the cells
-            // of bricks that hold markers or whose colours / markers changed (a
-            // cell also reads the edges stored at its upper neighbours)
+            const bool fnode = task[2] || task[3];
+            if (!fnode) a.flo[qs] = out;
+            // queue: unaligned markers of both planes, then the face nodes and their faces
+            {
+                const unsigned long long lt = (1ull << lane) - 1ull;
+                unsigned long long bal = __ballot(task[0]);
+                if (task[0]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = 0; }
+                ntask += __popcll(bal);
+                bal = __ballot(task[1]);
+                if (task[1]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = 1; }
+                ntask += __popcll(bal);
+                bal = __ballot(fnode);
+                const int slot = nslot + __popcll(bal & lt);
+                if (fnode) { sq[slot] = (uint32_t)qs; sb[slot] = out; }
+                nslot += __popcll(bal);
+                bal = __ballot(task[2]);
+                if (task[2]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = (uint8_t)(2 | (c00 << 2)); ts[i] = (uint8_t)slot; }
+                ntask += __popcll(bal);
+                bal = __ballot(task[3]);
+                if (task[3]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = (uint8_t)(3 | (c00 << 2)); ts[i] = (uint8_t)slot; }
+                ntask += __popcll(bal);
+            }
+            // lists: the next sweep takes the bricks next to a brick holding
+            // markers now; Front2VOF revisits the cells of bricks that hold
+            // markers or whose colours / markers changed (a cell also reads the
+            // edges stored at its upper neighbours)
             const bool hasm = __ballot((out & 0x70) != 0) != 0;
             const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
-            if (hasm && lane < 27) cm_next[brick_shift(b, nb1, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1)] = t + 1;
-            if ((hasm || chg) && lane >= 32 && lane < 40) {
-                int d = lane - 32;
-                a.w.fmark[brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2))] = a.fgen;
+            if (lane == 0) {
+                if (hasm) mbr[nm] = b;
+                if (hasm || chg) cbr[nc] = b;
             }
+            nm += hasm ? 1 : 0;
+            nc += (hasm || chg) ? 1 : 0;
             fbc += fb;
             cflc += cfl;
             mergedc += merged;
             __syncthreads();   // the tile is reused by the next brick
         }
-        // the chunk's task counts and counters (this workgroup owns the chunk)
-        fbc = wave_sum(fbc);
-        cflc = wave_sum(cflc);
-        mergedc = wave_sum(mergedc);
-        if (lane < 4) {
-            const int v = lane == 0 ? nt[0] : (lane == 1 ? nt[1] : (lane == 2 ? nt[2] : nt[3]));
-            a.w.tcnt[lane * nc + ch] = (uint32_t)v;
-        }
-        if (lane == 0) {
-            a.w.cs[CS_FALLBACK * nc + ch] += (unsigned long long)fbc;
-            a.w.cs[CS_CFL * nc + ch] += (unsigned long long)cflc;
-            a.w.cs[CS_MERGED * nc + ch] += (unsigned long long)mergedc;
-            a.w.cs[CS_ACTIVE * nc + ch] += (unsigned long long)nact * 64ull;
-        }
     }
-}
-
-// Old-state accessor for phase B: global memory, periodic, offsets relative
-// to the task's node in the plane (D, A).
-template <typename T, int D, int A>
-struct GlobAcc {
-    static constexpr int B = 3 - D - A;
-    const uint8_t *__restrict__ fl;
-    const T *__restrict__ sD;
-    const T *__restrict__ sA;
-    const T *__restrict__ U;
-    T c;
-    int n;
-    int ci, cj;
-    long base, strD, strA;
-    __device__ __forceinline__ long node(int i, int j) const
-    {
-        return (long)wrp(ci + i, n) * strD + (long)wrp(cj + j, n) * strA + base;
-    }
-    __device__ __forceinline__ uint8_t f(int i, int j) const { return fl[node(i, j)]; }
-    __device__ __forceinline__ double xd(int i, int j) const
-    {
-        long q = node(i, j);
-        T s = sD[q];
-        T U0 = U[q];
-        T u = U0 + s * (U[node(i + 1, j)] - U0);
-        T del = c * u;
-        return (double)s + (double)del;
-    }
-    __device__ __forceinline__ double dva(int i, int j) const
-    {
-        long q = node(i, j);
-        T s = sA[q];
-        T U0 = U[q];
-        T u = U0 + s * (U[node(i, j + 1)] - U0);
-        return (double)(c * u);
-    }
-    __device__ __forceinline__ T sa(int i, int j) const { return sA[node(i, j)]; }
-};
-
-template <typename T, int D, int A>
-__device__ __forceinline__ PlaneAlg<T, D, A, GlobAcc<T, D, A>> plane_at(const SweepArgs<T> &a, long q)
-{
-    constexpr int B = 3 - D - A;
-    const int n = a.g.n;
-    const long str[3] = {1, (long)n, a.g.nn};
-    int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / a.g.nn)};
-    GlobAcc<T, D, A> g;
-    g.fl = a.fl; g.sD = a.s[D]; g.sA = a.s[A]; g.U = a.U; g.c = a.c; g.n = n;
-    g.ci = P[D]; g.cj = P[A]; g.base = (long)P[B] * str[B]; g.strD = str[D]; g.strA = str[A];
-    return PlaneAlg<T, D, A, GlobAcc<T, D, A>>{g};
-}
-
-// Phase B: the chunks' task segments, one task per lane: circle-fit placement
-// of each new unaligned marker (sec. 2.1) and the colour of each face whose
-// corners differ (phase A wrote every other output).
-template <typename T, int D>
-__global__ __launch_bounds__(64) void k_sweep_b(SweepArgs<T> a)
-{
-    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
-    const int nc = a.g.nc;
-    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
-        uint32_t c[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = min(a.w.tcnt[k * nc + ch], (uint32_t)kSeg);
-        const uint32_t total = c[0] + c[1] + c[2] + c[3];
-        int fbt = 0, multit = 0;
-        for (uint32_t i = threadIdx.x; i < total; i += 64) {
-            uint32_t k = i;
-            int type = 0;
-            if (k >= c[0]) { k -= c[0]; type = 1;
-                if (k >= c[1]) { k -= c[1]; type = 2;
-                    if (k >= c[2]) { k -= c[2]; type = 3; } } }
-            const long q = (long)a.w.task[type][(size_t)ch * kSeg + k];
-            if (type == 0) {
-                a.so[A1][q] = plane_at<T, D, A1>(a, q).unaligned(fbt, multit);
-            } else if (type == 1) {
-                a.so[A2][q] = plane_at<T, D, A2>(a, q).unaligned(fbt, multit);
-            } else {
-                const int c00 = a.flo[q] & 1;
-                int fc = type == 2 ? plane_at<T, D, A1>(a, q).face_colour(c00)
-                                   : plane_at<T, D, A2>(a, q).face_colour(c00);
-                if (fc) {
-                    // faces of one node are written by two tasks: OR into the byte's word
-                    const int bit = type == 2 ? 1 + A2 : 1 + A1;
-                    unsigned int *w = (unsigned int *)(a.flo + (q & ~3L));
-                    atomicOr(w, (unsigned int)(1u << bit) << (8 * (int)(q & 3)));
-                }
-            }
-        }
-        // per-chunk counters (this workgroup owns the chunk)
-        const int f = wave_sum(fbt), m = wave_sum(multit);
-        if (threadIdx.x == 0) {
-            if (f) a.w.cs[CS_FALLBACK * nc + ch] += (unsigned long long)f;
-            if (m) a.w.cs[CS_MULTI * nc + ch] += (unsigned long long)m;
-        }
+    run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
+    claims();
+    // this wave's counters (the wave owns its slot)
+    fbc = wave_sum(fbc + fbt);
+    cflc = wave_sum(cflc);
+    mergedc = wave_sum(mergedc);
+    multit = wave_sum(multit);
+    if (lane == 0) {
+        const int nwv = a.g.nw;
+        a.w.cs[CS_FALLBACK * nwv + wv] += (unsigned long long)fbc;
+        a.w.cs[CS_MULTI * nwv + wv] += (unsigned long long)multit;
+        a.w.cs[CS_CFL * nwv + wv] += (unsigned long long)cflc;
+        a.w.cs[CS_MERGED * nwv + wv] += (unsigned long long)mergedc;
+        a.w.cs[CS_ACTIVE * nwv + wv] += (unsigned long long)nact * 64ull;
     }
 }
 
@@ -781,6 +908,7 @@ __device__ __forceinline__ T cell_volume(const uint8_t f[8], int has, const T sv
     return C;
 }
 
+
 template <typename T>
 struct F2VArgs {
     Geo g;
@@ -793,9 +921,9 @@ struct F2VArgs {
 };
 
 // load the 8 corner flag bytes of cell q (corner k = ox + 2 oy + 4 oz)
-__device__ __forceinline__ void corner_flags(const uint8_t *__restrict__ fl, int n, long nn, int x, int y, int z,
-                                             uint8_t f[8], long qc[8])
+__device__ __forceinline__ void corner_index(int n, long nn, long q, long qc[8])
 {
+    const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
     const int x1 = x + 1 == n ? 0 : x + 1, y1 = y + 1 == n ? 0 : y + 1, z1 = z + 1 == n ? 0 : z + 1;
     qc[0] = x + (long)n * y + nn * z;
     qc[1] = x1 + (long)n * y + nn * z;
@@ -805,8 +933,6 @@ __device__ __forceinline__ void corner_flags(const uint8_t *__restrict__ fl, int
     qc[5] = x1 + (long)n * y + nn * z1;
     qc[6] = x + (long)n * y1 + nn * z1;
     qc[7] = x1 + (long)n * y1 + nn * z1;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) f[k] = fl[qc[k]];
 }
 
 // 12-bit marker mask of a cell; edge id 4e + oA + 2 oB starts at the corner
@@ -823,80 +949,135 @@ __device__ __forceinline__ int marker_mask(const uint8_t f[8])
     return has;
 }
 
-// Front2VOF phase A, one 64-lane workgroup per chunk: a cell of a brick to
-// revisit that carries no marker is full or empty (its corner colour); the
-// others go to the chunk's interfacial-cell segment.
-template <typename T>
-__global__ __launch_bounds__(64) void k_f2v_a(F2VArgs<T> a)
+// corner of the cell at which marker edge `id` starts
+__device__ __forceinline__ int edge_corner(int id)
 {
+    const int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
+    const int cx = e == 0 ? 0 : oA, cy = e == 1 ? 0 : (e == 0 ? oA : oB), cz = e == 2 ? 0 : oB;
+    return cx + 2 * cy + 4 * cz;
+}
+
+// Volume fractions of queued interfacial cells (one per lane, first `cnt`
+// entries of the queue; flags from the queue, fractions from memory).
+// Returns the number of ambiguous cells among them.
+template <typename T>
+__device__ __forceinline__ int f2v_cells(const F2VArgs<T> &a, const uint32_t *cq, const uint64_t *cf, int cnt)
+{
+    const int lane = threadIdx.x & 63;
+    int amb = 0;
+    if (lane < cnt) {
+        const long q = cq[lane];
+        const uint64_t pk = cf[lane];
+        uint8_t f[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f[k] = (uint8_t)(pk >> (8 * k));
+        long qc[8];
+        corner_index(a.g.n, a.g.nn, q, qc);
+        const int has = marker_mask(f);
+        T sv[12];
+#pragma unroll
+        for (int id = 0; id < 12; ++id) sv[id] = ((has >> id) & 1) ? a.s[id >> 2][qc[edge_corner(id)]] : T(0);
+        a.C[q] = cell_volume<T>(f, has, sv, amb);
+    }
+    return wave_sum(amb);
+}
+
+// Front2VOF, wave w over items w, w + nw, ... of the revisit list (or every
+// brick): a cell without a marker is full or empty (its corner colour); the
+// others are queued, their volume fractions computed 64 at a time, and listed
+// in the wave's interfacial-cell segment (the cells of this Front2VOF, for
+// the surrogate and its training rows).  With `classify` set only the
+// segment is written for the interfacial cells.
+template <typename T>
+__global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int classify)
+{
+    __shared__ uint32_t cq[kCellCap];
+    __shared__ uint64_t cf[kCellCap];
     const int lane = threadIdx.x;
-    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb, nc = a.g.nc;
+    const int wv = blockIdx.x, nw = gridDim.x;
+    const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const long nn = a.g.nn;
-    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
-        bool valid;
-        const int bl = chunk_brick(a.g, ch, lane, valid);
-        const bool act = valid && (a.full || a.w.fmark[bl] == a.gen);
-        unsigned long long pending = __ballot(act);
-        int np = 0;
-        long long delta = 0;    // change of the chunk's interfacial-cell count
-        while (pending) {
-            const int k = __ffsll((long long)pending) - 1;
-            pending &= pending - 1;
-            const int b = __shfl(bl, k);
+    const uint32_t gen = a.gen;
+    if (wv == 0 && lane < kSub) a.w.fnum[((gen + 1) % 2) * kSub + lane] = 0;   // the next generation starts empty
+    Items it;
+    if (a.full) {
+        it.total = (uint32_t)nb;
+    } else {
+        it.init(a.w.fnum + (gen % 2) * kSub, nullptr, a.w.flist[gen % 2], nullptr, (uint32_t)nb);
+    }
+    uint32_t *seg = a.w.ctask + (size_t)wv * a.g.segcap;
+    long np = 0;
+    int nq = 0, ambc = 0;
+    long long delta = 0;
+    const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
+    for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
+        int bl = -1;
+        {
+            const uint32_t i = i0 + (uint32_t)lane;
+            const uint32_t k = (uint32_t)wv + i * (uint32_t)nw;
+            const bool have = i < mine;
+            int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
+            if (!have || bb < 0 || bb >= nb) bb = -1;
+            bl = bb;
+        }
+        unsigned long long pend = __ballot(bl >= 0);
+        while (pend) {
+            const int src = __ffsll((long long)pend) - 1;
+            pend &= pend - 1;
+            const int b = __shfl(bl, src);
             const int x = (b % nb1) * 4 + (lane & 3), y = ((b / nb1) % nb1) * 4 + ((lane >> 2) & 3),
                       z = (b / (nb1 * nb1)) * 4 + (lane >> 4);
-            uint8_t f[8];
+            const long q = x + (long)n * y + nn * z;
             long qc[8];
-            corner_flags(a.fl, n, nn, x, y, z, f, qc);
+            corner_index(n, nn, q, qc);
+            uint8_t f[8];
+    #pragma unroll
+            for (int kk = 0; kk < 8; ++kk) f[kk] = a.fl[qc[kk]];
             const int has = marker_mask(f);
-            if (!has) a.C[qc[0]] = (T)(f[0] & 1);
-            wave_put(a.w.ctask + (size_t)ch * kSeg, np, has != 0, (uint32_t)qc[0]);
-            const int nb_int = __popcll(__ballot(has != 0));
-            if (lane == 0) {
-                delta += (long long)nb_int - (long long)a.w.bcnt[b];
-                a.w.bcnt[b] = (uint32_t)nb_int;
+            if (!has) a.C[q] = (T)(f[0] & 1);
+            const unsigned long long bal = __ballot(has != 0);
+            const int r = __popcll(bal & ((1ull << lane) - 1ull));
+            if (has) {
+                uint64_t pk = 0;
+    #pragma unroll
+                for (int kk = 0; kk < 8; ++kk) pk |= (uint64_t)f[kk] << (8 * kk);
+                cq[nq + r] = (uint32_t)q;
+                cf[nq + r] = pk;
+                if (np + r < a.g.segcap) seg[np + r] = (uint32_t)q;
+            }
+            const int cnt = __popcll(bal);
+            nq += cnt;
+            np += cnt;
+            delta += (long long)cnt - (long long)a.w.bcnt[b];
+            __syncthreads();
+            if (lane == 0) a.w.bcnt[b] = (uint32_t)cnt;
+            if (classify) {
+                nq = 0;
+            } else if (nq >= 64) {
+                ambc += f2v_cells<T>(a, cq, cf, 64);
+                __syncthreads();
+                const int rest = nq - 64;
+                uint32_t mq = 0;
+                uint64_t mf = 0;
+                if (lane < rest) { mq = cq[64 + lane]; mf = cf[64 + lane]; }
+                __syncthreads();
+                if (lane < rest) { cq[lane] = mq; cf[lane] = mf; }
+                __syncthreads();
+                nq = rest;
             }
         }
-        if (lane == 0) {
-            a.w.ccnt[ch] = (uint32_t)np;
-            unsigned long long cur = (unsigned long long)((long long)a.w.cs[CS_INTER * nc + ch] + delta);
-            a.w.cs[CS_INTER * nc + ch] = cur;
-            a.w.cs[CS_INTER_SUM * nc + ch] += cur;
-        }
+    }
+    if (!classify && nq > 0) ambc += f2v_cells<T>(a, cq, cf, nq);
+    if (lane == 0) {
+        const int nwv = a.g.nw;
+        a.w.ccnt[wv] = (uint32_t)(np < a.g.segcap ? np : a.g.segcap);
+        const unsigned long long cur = (unsigned long long)((long long)a.w.cs[CS_INTER * nwv + wv] + delta);
+        a.w.cs[CS_INTER * nwv + wv] = cur;
+        a.w.cs[CS_INTER_SUM * nwv + wv] += cur;
+        if (!classify) a.w.cs[CS_AMB * nwv + wv] = (unsigned long long)ambc;
     }
 }
 
-// Front2VOF phase B: one interfacial cell per lane.
-template <typename T>
-__global__ __launch_bounds__(64) void k_f2v_b(F2VArgs<T> a)
-{
-    const int n = a.g.n, nc = a.g.nc;
-    const long nn = a.g.nn;
-    for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
-        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
-        int ambc = 0;
-        for (uint32_t i = threadIdx.x; i < count; i += 64) {
-            const long q = (long)a.w.ctask[(size_t)ch * kSeg + i];
-            const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
-            uint8_t f[8];
-            long qc[8];
-            corner_flags(a.fl, n, nn, x, y, z, f, qc);
-            const int has = marker_mask(f);
-            T sv[12];
-#pragma unroll
-            for (int id = 0; id < 12; ++id) {
-                int e = id >> 2, oA = id & 1, oB = (id >> 1) & 1;
-                int cx = e == 0 ? 0 : oA, cy = e == 1 ? 0 : (e == 0 ? oA : oB), cz = e == 2 ? 0 : oB;
-                sv[id] = ((has >> id) & 1) ? a.s[e][qc[cx + 2 * cy + 4 * cz]] : T(0);
-            }
-            int amb = 0;
-            a.C[q] = cell_volume<T>(f, has, sv, amb);
-            ambc += amb;
-        }
-        const int s = wave_sum(ambc);
-        if (threadIdx.x == 0) a.w.cs[CS_AMB * nc + ch] = (unsigned long long)s;
-    }
-}
 
 // Topology of a cell from flags alone (sec. 2.4): a face with four markers,
 // or face segments that close into more than one loop, make the cell
@@ -945,11 +1126,10 @@ __device__ __forceinline__ int cell_ambiguous(const uint8_t f[8], int has)
 template <typename T>
 __device__ __forceinline__ int load_cell(const F2VArgs<T> &a, long q, uint8_t f[8], T sv[12])
 {
-    const int n = a.g.n;
-    const long nn = a.g.nn;
-    const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
     long qc[8];
-    corner_flags(a.fl, n, nn, x, y, z, f, qc);
+    corner_index(a.g.n, a.g.nn, q, qc);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] = a.fl[qc[k]];
     const int has = marker_mask(f);
 #pragma unroll
     for (int id = 0; id < 12; ++id) {
@@ -975,7 +1155,7 @@ __device__ __forceinline__ void put_features(__bf16 *row, const uint8_t f[8], co
 // Front2VOF phase B with the learned surrogate: unambiguous interfacial cells
 // take the network's volume fraction, computed on matrix cores 16 cells at a
 // time; ambiguous ones fall back to the geometric construction.  One wave per
-// chunk; the block's four waves share the weights in LDS.
+// interfacial-cell segment; the block's four waves share the weights in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *__restrict__ theta)
 {
@@ -988,9 +1168,9 @@ __global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *_
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
-    const int nc = a.g.nc;
+    const int nc = a.g.nw;
     for (int ch = blockIdx.x * 4 + wave; ch < nc; ch += gridDim.x * 4) {
-        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
+        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)a.g.segcap);
         int ambc = 0;
         for (uint32_t base = 0; base < count; base += 64) {
             const uint32_t i = base + lane;
@@ -1000,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *_
             T sv[12];
             int has = 0, amb = 0;
             if (valid) {
-                q = (long)a.w.ctask[(size_t)ch * kSeg + i];
+                q = (long)a.w.ctask[(size_t)ch * a.g.segcap + i];
                 has = load_cell<T>(a, q, f, sv);
                 amb = cell_ambiguous(f, has);
             }
@@ -1039,16 +1219,16 @@ __global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *_
     }
 }
 
-// Surrogate training rows: per chunk, the unambiguous interfacial cells of
+// Surrogate training rows: per segment, the unambiguous interfacial cells of
 // the last Front2VOF (count pass, then write pass at host-computed offsets).
 template <typename T>
 __global__ __launch_bounds__(64) void k_dataset(F2VArgs<T> a, int write, uint16_t *__restrict__ xout,
                                                 float *__restrict__ cout, long cap)
 {
     const int lane = threadIdx.x;
-    const int nc = a.g.nc;
+    const int nc = a.g.nw;
     for (int ch = blockIdx.x; ch < nc; ch += gridDim.x) {
-        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)kSeg);
+        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)a.g.segcap);
         long pos = write ? a.w.doff[ch] : 0;
         for (uint32_t base = 0; base < count; base += 64) {
             const uint32_t i = base + lane;
@@ -1057,7 +1237,7 @@ __global__ __launch_bounds__(64) void k_dataset(F2VArgs<T> a, int write, uint16_
             T sv[12];
             int has = 0, amb = 1;
             if (valid) {
-                has = load_cell<T>(a, (long)a.w.ctask[(size_t)ch * kSeg + i], f, sv);
+                has = load_cell<T>(a, (long)a.w.ctask[(size_t)ch * a.g.segcap + i], f, sv);
                 amb = cell_ambiguous(f, has);
             }
             const bool take = valid && !amb;
@@ -1079,14 +1259,14 @@ __global__ __launch_bounds__(64) void k_dataset(F2VArgs<T> a, int write, uint16_
     }
 }
 
-// totals of the per-chunk counters (integer sums: order-free)
+// totals of the per-wave counters (integer sums: order-free)
 __global__ __launch_bounds__(256) void k_stats_reduce(Work w, Geo g)
 {
     __shared__ unsigned long long red[CS_COUNT][4];
     unsigned long long acc[CS_COUNT];
     for (int k = 0; k < CS_COUNT; ++k) acc[k] = 0;
-    for (int ch = threadIdx.x; ch < g.nc; ch += blockDim.x)
-        for (int k = 0; k < CS_COUNT; ++k) acc[k] += w.cs[k * g.nc + ch];
+    for (int ch = threadIdx.x; ch < g.nw; ch += blockDim.x)
+        for (int k = 0; k < CS_COUNT; ++k) acc[k] += w.cs[k * g.nw + ch];
     for (int k = 0; k < CS_COUNT; ++k) {
         unsigned long long v = acc[k];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -1176,7 +1356,6 @@ __global__ void k_zero_marks(unsigned long long *stat)
 }
 
 }  // namespace
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -1195,8 +1374,10 @@ struct ebit_ctx {
     int full;              // process every brick
     const void *lastC;     // C array of the previous Front2VOF
     const float *surr;     // surrogate parameters (NULL: geometric Front2VOF only)
-    int grid_a;            // phase-A grid (64-lane workgroups)
-    int grid_b;            // phase-B grid (256-lane blocks)
+    int timing;            // bracket launches with events
+    hipEvent_t *ev;        // 2 * kTimed events
+    uint8_t *ev_kind;      // 0 sweep, 1 Front2VOF
+    int ev_n;              // launches recorded since the last ebit_timing
 };
 
 namespace {
@@ -1215,6 +1396,22 @@ int check_launch()
 
 int clampi(int v, int hi) { return v < hi ? (v > 0 ? v : 1) : hi; }
 
+constexpr int kTimed = 8192;   // launches timed between two ebit_timing calls
+
+bool timed(const ebit_ctx *c) { return c->timing && c->ev && c->ev_n < kTimed; }
+
+void time_begin(ebit_ctx *c, hipStream_t st)
+{
+    if (timed(c)) (void)hipEventRecord(c->ev[2 * c->ev_n], st);
+}
+
+void time_end(ebit_ctx *c, hipStream_t st, int kind)
+{
+    if (!timed(c)) return;
+    (void)hipEventRecord(c->ev[2 * c->ev_n + 1], st);
+    c->ev_kind[c->ev_n++] = (uint8_t)kind;
+}
+
 template <typename T, int D>
 void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
 {
@@ -1232,8 +1429,9 @@ void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
     a.t = c->t;
     a.fgen = c->fgen;
     a.full = c->full;
-    hipLaunchKernelGGL((k_sweep_a<T, D>), dim3(clampi(c->g.nc, c->grid_a)), dim3(64), 0, st, a);
-    hipLaunchKernelGGL((k_sweep_b<T, D>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
+    time_begin(c, st);
+    hipLaunchKernelGGL((k_sweep<T, D>), dim3(c->g.nw), dim3(64), 0, st, a);
+    time_end(c, st, 0);
 }
 
 template <typename T>
@@ -1262,11 +1460,11 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     a.w = c->w;
     a.gen = c->fgen;
     a.full = full;
-    hipLaunchKernelGGL((k_f2v_a<T>), dim3(clampi(c->g.nc, c->grid_a)), dim3(64), 0, st, a);
+    time_begin(c, st);
+    hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
-        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nc + 3) / 4, 256 * 2)), dim3(256), 0, st, a, c->surr);
-    else
-        hipLaunchKernelGGL((k_f2v_b<T>), dim3(clampi(c->g.nc, c->grid_b)), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + 3) / 4, 256 * 2)), dim3(256), 0, st, a, c->surr);
+    time_end(c, st, 1);
     c->fgen++;
     c->last_t_f2v = c->t;
     c->lastC = C;
@@ -1285,10 +1483,10 @@ int dataset_impl(ebit_ctx *c, void *x_bf16, float *cout, int64_t cap, int64_t *c
     a.w = c->w;
     a.gen = c->fgen - 1;
     a.full = 0;
-    int grid = clampi(c->g.nc, c->grid_a);
+    int grid = c->g.nw;
     hipLaunchKernelGGL((k_dataset<T>), dim3(grid), dim3(64), 0, st, a, 0, (uint16_t *)nullptr, (float *)nullptr, 0L);
     if (check_launch() != EBIT_OK) return EBIT_EHIP;
-    const int nc = c->g.nc;
+    const int nc = c->g.nw;
     uint32_t *hc = (uint32_t *)malloc((size_t)nc * 4);
     long long *ho = (long long *)malloc((size_t)nc * 8);
     if (!hc || !ho) { free(hc); free(ho); return EBIT_EINVAL; }
@@ -1338,7 +1536,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
               const double *const *s_exact, void *stream)
 {
     if (!out || !d) return EBIT_EINVAL;
-    if (d->n < 8 || d->n % 4 || d->n > 2048) return EBIT_EINVAL;
+    if (d->n < 8 || d->n % 4 || d->n > 1024) return EBIT_EINVAL;
     if (d->precision != EBIT_FP64 && d->precision != EBIT_FP32) return EBIT_EINVAL;
     for (int b = 0; b < 2; ++b) {
         if (!d->flags[b]) return EBIT_EINVAL;
@@ -1365,23 +1563,14 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->g.nn = (long)d->n * d->n;
     int nbricks = c->g.nb1 * c->g.nb1 * c->g.nb1;
     c->g.nb = nbricks;
-    c->g.nc = chunks_for(d->n);
-    {
-        // hash multiplier: a prime above the brick count (hence coprime with it)
-        long p = 1000003;
-        while (p <= nbricks) p = p * 2 + 1;
-        auto isprime = [](long v) { for (long q = 3; q * q <= v; q += 2) if (v % q == 0) return false; return (v & 1) != 0; };
-        while (!isprime(p)) p += 2;
-        c->g.hmul = p % nbricks == 0 ? 1 : p;
-    }
+    c->g.nw = waves_for(d->n);
+    c->g.segcap = segcap_for(d->n);
     c->t = 2;
     c->fgen = 1;
     c->last_t_f2v = 0;
     c->full = 0;
     c->lastC = nullptr;
     c->surr = nullptr;
-    c->grid_a = 256 * 24;       // persistent: 24 single-wave workgroups per CU
-    c->grid_b = 256 * 16;       // 16 single-wave workgroups per CU
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
@@ -1406,7 +1595,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
         return EBIT_EHIP;
     }
     hipLaunchKernelGGL(k_zero_work, dim3((c->g.nb + 255) / 256), dim3(256), 0, st, c->w, c->g);
-    hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, c->grid_a)), dim3(64), 0, st, c->g, c->flags[0], c->w);
+    hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, kMaxWaves)), dim3(64), 0, st, c->g, c->flags[0], c->w);
     int rc = check_launch();
     if (rc != EBIT_OK) {
         free(c);
@@ -1494,9 +1683,71 @@ int ebit_set_option(ebit_ctx *c, int option, int value)
         c->full = value != 0;
         return EBIT_OK;
     }
+    if (option == EBIT_OPT_TIMING) {
+        if (value && !c->ev) {
+            hipEvent_t *ev = (hipEvent_t *)calloc(2 * kTimed, sizeof(hipEvent_t));
+            uint8_t *kind = (uint8_t *)calloc(kTimed, 1);
+            if (!ev || !kind) { free(ev); free(kind); return EBIT_EINVAL; }
+            for (int k = 0; k < 2 * kTimed; ++k) {
+                if (hipEventCreate(&ev[k]) != hipSuccess) {
+                    for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+                    free(ev);
+                    free(kind);
+                    return EBIT_EHIP;
+                }
+            }
+            c->ev = ev;
+            c->ev_kind = kind;
+            c->ev_n = 0;
+        }
+        c->timing = value != 0;
+        return EBIT_OK;
+    }
     return EBIT_EINVAL;
 }
 
-void ebit_destroy(ebit_ctx *c) { free(c); }
+int ebit_timing(ebit_ctx *c, ebit_timing_t *out)
+{
+    if (!c || !out) return EBIT_EINVAL;
+    memset(out, 0, sizeof(*out));
+    if (!c->ev || c->ev_n == 0) return EBIT_OK;
+    if (hipEventSynchronize(c->ev[2 * c->ev_n - 1]) != hipSuccess) return EBIT_EHIP;
+    for (int k = 0; k < c->ev_n; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess) return EBIT_EHIP;
+        if (c->ev_kind[k] == 0) { out->sweeps++; out->sweep_ms += ms; }
+        else { out->f2v++; out->f2v_ms += ms; }
+    }
+    c->ev_n = 0;
+    return EBIT_OK;
+}
+
+int ebit_advance(ebit_ctx *c, int32_t nsteps, const void *const *U, const double *g, double dt, void *C,
+                 void *stream)
+{
+    if (!c || nsteps < 0 || !U || !U[0] || !U[1] || !U[2] || (nsteps > 0 && !g)) return EBIT_EINVAL;
+    for (int k = 0; k < nsteps; ++k) {
+        for (int d = 0; d < 3; ++d) {
+            int rc = ebit_advect_sweep(c, d, U[d], g[k], dt, stream);
+            if (rc != EBIT_OK) return rc;
+        }
+        if (C) {
+            int rc = ebit_front2vof(c, C, stream);
+            if (rc != EBIT_OK) return rc;
+        }
+    }
+    return EBIT_OK;
+}
+
+void ebit_destroy(ebit_ctx *c)
+{
+    if (!c) return;
+    if (c->ev) {
+        for (int k = 0; k < 2 * kTimed; ++k) (void)hipEventDestroy(c->ev[k]);
+        free(c->ev);
+        free(c->ev_kind);
+    }
+    free(c);
+}
 
 }  // extern "C"

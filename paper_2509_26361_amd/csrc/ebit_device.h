@@ -93,57 +93,69 @@ __device__ __forceinline__ T fit_height(T P1x, T P1y, T P2x, T P2y, T P3x, T P3y
     return clamp_frac<T>(y);
 }
 
-// One 2D problem of a sweep (paper sec. 2.3): the plane spanned by the sweep
-// axis D ("X") and axis A ("Y") through a node.  Offsets (i, j) are relative
-// to that node.  Horizontal edges H(i,j) run along D (aligned markers),
-// vertical edges V(i,j) along A (unaligned); face Q(i,j) spans [i,i+1] x
-// [j,j+1] and has normal B.  The accessor `Acc` supplies, per node offset:
-//   f(i,j)    old flags (bit 7: the node's new colour after this sweep)
-//   xd(i,j)   s + delta of the D-edge marker (decision precision, double)
-//   dva(i,j)  delta of the A-edge marker (double)
-//   sa(i,j)   fraction of the A-edge marker
-template <typename T, int D, int A, class Acc>
-struct PlaneAlg {
-    static constexpr int B = 3 - D - A;
-    Acc acc;
+// One 2D problem of a sweep (paper sec. 2.3) seen from one task node: the
+// plane spanned by the sweep axis D ("X") and an axis A ("Y", chosen at run
+// time) through the node.  Offsets (i, j) are relative to the node.
+// Horizontal edges H(i,j) run along D (aligned markers), vertical edges V(i,j)
+// along A (unaligned); face Q(i,j) spans [i,i+1] x [j,j+1] and has normal B.
+// Everything is read from the old state in global memory, in three rounds of
+// independent loads: the flags of offsets i in [-3, 2], j in [-1, 2]; then the
+// markers of the three candidate faces; then, for a new unaligned marker, the
+// two polyline neighbours of the chosen segment.
+template <typename T, int D>
+struct PlaneTask {
+    const uint8_t *__restrict__ fl;
+    const T *__restrict__ sD;     // fractions of the H markers
+    const T *__restrict__ sA;     // fractions of the V markers
+    const T *__restrict__ U;      // D-velocity at nodes
+    T c;                          // (dt n) g
+    int n;
+    int ci, cj;                   // the node's coordinates along D and A
+    long strD, strA, base;        // index strides of D and A; offset of the B coordinate
+    int hb, vb, fb;               // flag bits: H marker, V marker, colour of Q(i,j)
+    // bits of the flags of offsets i = -3..2, j = -1..2 at bit (i + 3) + 6 (j + 1):
+    uint32_t mH, mV, mF, mC;      // H marker, V marker, colour of Q(i,j), node colour
 
-    __device__ __forceinline__ uint8_t f(int i, int j) const { return acc.f(i, j); }
-    __device__ __forceinline__ int ncol(int i, int j) const { return (acc.f(i, j) >> 7) & 1; }
-    __device__ __forceinline__ bool hhas(int i, int j) const { return (acc.f(i, j) >> (4 + D)) & 1; }
-    __device__ __forceinline__ bool vhas(int i, int j) const { return (acc.f(i, j) >> (4 + A)) & 1; }
-
-    // advected marker of a side, relative to the reference node
-    // sides: 0 bottom H(fi,fj), 1 right V(fi+1,fj), 2 top H(fi,fj+1), 3 left V(fi,fj)
-    __device__ __forceinline__ void point(int fi, int fj, int side, double &X, double &Y) const
+    __device__ __forceinline__ long node(int i, int j) const
     {
-        switch (side) {
-        case 0: X = (double)fi + acc.xd(fi, fj); Y = (double)fj; break;
-        case 2: X = (double)fi + acc.xd(fi, fj + 1); Y = (double)(fj + 1); break;
-        case 3: X = (double)fi + acc.dva(fi, fj); Y = (double)fj + (double)acc.sa(fi, fj); break;
-        default: X = (double)(fi + 1) + acc.dva(fi + 1, fj); Y = (double)fj + (double)acc.sa(fi + 1, fj); break;
+        return (long)wrp(ci + i, n) * strD + (long)wrp(cj + j, n) * strA + base;
+    }
+    static __device__ __forceinline__ int bit(int i, int j) { return (i + 3) + 6 * (j + 1); }
+    __device__ __forceinline__ void fetch_flags()
+    {
+        uint32_t b[24];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) b[i + 6 * j] = fl[node(i - 3, j - 1)];
+        mH = mV = mF = mC = 0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            mH |= ((b[k] >> hb) & 1u) << k;
+            mV |= ((b[k] >> vb) & 1u) << k;
+            mF |= ((b[k] >> fb) & 1u) << k;
+            mC |= (b[k] & 1u) << k;
         }
     }
-
-    // segments of face Q(fi,fj) from the old state (paper sec. 2.2, 2.4),
-    // packed: bits 0-1 / 2-3 the sides of the first segment (lower first), bits
-    // 4-5 / 6-7 the second; bits 8-9 the number of segments.  The segment
-    // through side 0 comes first.
+    __device__ __forceinline__ int hhas(int i, int j) const { return (mH >> bit(i, j)) & 1; }
+    __device__ __forceinline__ int vhas(int i, int j) const { return (mV >> bit(i, j)) & 1; }
+    // segments of Q(fi,fj) in the old state (sec. 2.2, 2.4), packed: bits 0-1 /
+    // 2-3 the sides of the first segment (lower first), 4-5 / 6-7 the second,
+    // 8-9 the number of segments.  A four-marker face cuts off the corners
+    // whose colour differs from its centre colour.
     __device__ __forceinline__ int pairs(int fi, int fj) const
     {
-        uint8_t f00 = f(fi, fj), f10 = f(fi + 1, fj), f01 = f(fi, fj + 1);
-        int h0 = (f00 >> (4 + D)) & 1, v1 = (f10 >> (4 + A)) & 1;
-        int h2 = (f01 >> (4 + D)) & 1, v3 = (f00 >> (4 + A)) & 1;
-        int m = h0 + v1 + h2 + v3;
+        const int k00 = bit(fi, fj);
+        const int h0 = (mH >> k00) & 1, v1 = (mV >> (k00 + 1)) & 1;
+        const int h2 = (mH >> (k00 + 6)) & 1, v3 = (mV >> k00) & 1;
+        const int m = h0 + v1 + h2 + v3;
         if (m == 2) {
-            // the two sides present, lower first
-            int lo = h0 ? 0 : (v1 ? 1 : 2);
-            int hi = v3 ? 3 : (h2 ? 2 : 1);
+            const int lo = h0 ? 0 : (v1 ? 1 : 2);
+            const int hi = v3 ? 3 : (h2 ? 2 : 1);
             return lo | (hi << 2) | (1 << 8);
         }
         if (m == 4) {
-            int c00 = f00 & 1;
-            int ff = (f00 >> (1 + B)) & 1;
-            // corners (1,0),(0,1) cut off: (0,1),(2,3); else corners (0,0),(1,1): (0,3),(1,2)
+            const int c00 = (mC >> k00) & 1, ff = (mF >> k00) & 1;
             return ff == c00 ? (0 | (1 << 2) | (2 << 4) | (3 << 6) | (2 << 8))
                              : (0 | (3 << 2) | (1 << 4) | (2 << 6) | (2 << 8));
         }
@@ -153,55 +165,142 @@ struct PlaneAlg {
     static __device__ __forceinline__ int side_a(int pk, int t) { return (pk >> (4 * t)) & 3; }
     static __device__ __forceinline__ int side_b(int pk, int t) { return (pk >> (4 * t + 2)) & 3; }
 
-    // far end, in the neighbouring face, of the segment through `side`'s marker
-    __device__ __forceinline__ void neighbour(int fi, int fj, int side, double &X, double &Y) const
+    // far end, in the neighbouring face, of the segment through `side`'s
+    // marker: the face (ni, nj) and its side
+    __device__ __forceinline__ void neighbour(int fi, int fj, int side, int &ni, int &nj, int &other) const
     {
-        int ni = fi, nj = fj, ns;
-        switch (side) {
-        case 0: nj = fj - 1; ns = 2; break;
-        case 2: nj = fj + 1; ns = 0; break;
-        case 1: ni = fi + 1; ns = 3; break;
-        default: ni = fi - 1; ns = 1; break;
-        }
-        int pk = pairs(ni, nj);
-        int other = ns;
+        ni = side == 1 ? fi + 1 : (side == 3 ? fi - 1 : fi);
+        nj = side == 0 ? fj - 1 : (side == 2 ? fj + 1 : fj);
+        const int ns = (side + 2) & 3;
+        const int pk = pairs(ni, nj);
+        other = ns;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             if (t >= nseg(pk)) break;
             if (side_a(pk, t) == ns) other = side_b(pk, t);
             else if (side_b(pk, t) == ns) other = side_a(pk, t);
         }
-        point(ni, nj, other, X, Y);
+    }
+    // where the marker of a side of Q(fi,fj) is stored: fraction array, its
+    // node, the node across the edge (for the velocity), and the point's
+    // integer offsets
+    __device__ __forceinline__ void locate(int fi, int fj, int side, bool &hz, long &q, long &q1, int &xi, int &yj) const
+    {
+        hz = side == 0 || side == 2;
+        xi = side == 1 ? fi + 1 : fi;
+        yj = side == 2 ? fj + 1 : fj;
+        q = node(xi, yj);
+        q1 = hz ? node(xi + 1, yj) : node(xi, yj + 1);
+    }
+    // advanced positions of two markers given by locate(), loads first
+    __device__ __forceinline__ void two_points(int fa, int fja, int sa, int fb, int fjb, int sb, double &Xa, double &Ya,
+                                              double &Xb, double &Yb) const
+    {
+        bool ha, hb;
+        long qa, qa1, qb, qb1;
+        int xa, ya, xb, yb;
+        locate(fa, fja, sa, ha, qa, qa1, xa, ya);
+        locate(fb, fjb, sb, hb, qb, qb1, xb, yb);
+        const T s_a = ha ? sD[qa] : sA[qa], s_b = hb ? sD[qb] : sA[qb];
+        const T ua0 = U[qa], ua1 = U[qa1], ub0 = U[qb], ub1 = U[qb1];
+        const T dela = c * (ua0 + s_a * (ua1 - ua0)), delb = c * (ub0 + s_b * (ub1 - ub0));
+        if (ha) { Xa = (double)xa + ((double)s_a + (double)dela); Ya = (double)ya; }
+        else { Xa = (double)xa + (double)dela; Ya = (double)ya + (double)s_a; }
+        if (hb) { Xb = (double)xb + ((double)s_b + (double)delb); Yb = (double)yb; }
+        else { Xb = (double)xb + (double)delb; Yb = (double)yb + (double)s_b; }
     }
 
-    // New marker on V(0,0) (called where the new end colours differ): crossings
-    // of X = 0 by advected old segments of faces -2..0 of the row; the median
-    // one (by height) is refined by the circle fit.
-    __device__ T unaligned(int &fallback, int &multi) const
+    // The task.  face = 0: the new marker on V(0,0) (the caller knows the new
+    // end colours differ): crossings of X = 0 by the advected old segments of
+    // faces -2..0 of the row; the median one (by height) is refined by the
+    // circle fit (sec. 2.1).  face = 1: colour at the centre of Q(0,0) relative
+    // to the advected polyline: start from the node's new colour c00, flip for
+    // aligned markers landing in [0, 1/2) on the bottom line and for advected
+    // segments of faces -1..1 crossing X = 1/2 below Y = 1/2.  Returns the
+    // fraction (face = 0) or the colour (face = 1).
+    __device__ __forceinline__ T run(int face, int c00, int &fallback, int &multi) const
     {
+        const int o0 = face ? -1 : -2;
+        const double x0 = face ? 0.5 : 0.0;
+        // markers of the candidate faces Q(o0+o, 0), o = 0..2 (X, Y relative to
+        // the node): the velocities at nodes (o0+k, r), k = 0..3, r = 0, 1 serve
+        // both edge families; every load is issued before any arithmetic (a
+        // missing marker reads a valid entry and is masked)
+        long qn[4][2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) qn[k][r] = node(o0 + k, r);
+        T Un[4][2], sh_[3][2], sv_[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) Un[k][r] = U[qn[k][r]];
+#pragma unroll
+        for (int o = 0; o < 3; ++o)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) sh_[o][r] = sD[qn[o][r]];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sv_[k] = sA[qn[k][0]];
+        double Hx[3][2], Vx[4], Vy[4];
+#pragma unroll
+        for (int o = 0; o < 3; ++o)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const T sx = sh_[o][r], u0 = Un[o][r];
+                const T del = c * (u0 + sx * (Un[o + 1][r] - u0));
+                Hx[o][r] = hhas(o0 + o, r) ? (double)(o0 + o) + ((double)sx + (double)del) : 0.0;
+            }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T sy = sv_[k], u0 = Un[k][0];
+            const T del = c * (u0 + sy * (Un[k][1] - u0));
+            const bool v = vhas(o0 + k, 0);
+            Vx[k] = v ? (double)(o0 + k) + (double)del : 0.0;
+            Vy[k] = v ? 0.0 + (double)sy : 0.0;
+        }
+        auto pt = [&](int o, int side, double &X, double &Y) {
+            X = side == 0 ? Hx[o][0] : (side == 2 ? Hx[o][1] : (side == 3 ? Vx[o] : Vx[o + 1]));
+            Y = side == 0 ? 0.0 : (side == 2 ? 1.0 : (side == 3 ? Vy[o] : Vy[o + 1]));
+        };
+        int par = c00;
+        if (face) {
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                if (!hhas(o0 + o, 0)) continue;
+                const double X = Hx[o][0];
+                if (0.0 <= X && X < 0.5) par ^= 1;
+            }
+        }
         T key[6];
         bool ok[6];
         int m = 0;
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
-            int pk = pairs(o - 2, 0);
+            const int pk = pairs(o0 + o, 0);
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 ok[2 * o + t] = false;
                 key[2 * o + t] = T(0);
                 if (t < nseg(pk)) {
                     double Ax, Ay, Bx, By;
-                    point(o - 2, 0, side_a(pk, t), Ax, Ay);
-                    point(o - 2, 0, side_b(pk, t), Bx, By);
-                    bool sa = 0.0 <= Ax, sb = 0.0 <= Bx;
+                    pt(o, side_a(pk, t), Ax, Ay);
+                    pt(o, side_b(pk, t), Bx, By);
+                    const bool sa = x0 <= Ax, sb = x0 <= Bx;
                     if (sa != sb) {
                         ok[2 * o + t] = true;
-                        key[2 * o + t] = sa ? line_cross<T>(T(0), (T)Bx, (T)By, (T)Ax, (T)Ay)
-                                            : line_cross<T>(T(0), (T)Ax, (T)Ay, (T)Bx, (T)By);
+                        key[2 * o + t] = sa ? line_cross<T>((T)x0, (T)Bx, (T)By, (T)Ax, (T)Ay)
+                                            : line_cross<T>((T)x0, (T)Ax, (T)Ay, (T)Bx, (T)By);
                         ++m;
                     }
                 }
             }
+        }
+        if (face) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (ok[k] && key[k] < T(0.5)) par ^= 1;
+            return (T)par;
         }
         if ((m & 1) == 0) {          // no odd crossing set: keep the edge valid
             fallback += 1;
@@ -218,52 +317,31 @@ struct PlaneAlg {
                 if (ok[c1] && (key[c1] < key[c0] || (key[c1] == key[c0] && c1 < c0))) ++rank;
             if (rank == (m >> 1)) pick = c0;
         }
-        int o = (pick >> 1) - 2, t = pick & 1;
-        int pk = pairs(o, 0);
-        int sa_ = side_a(pk, t), sb_ = side_b(pk, t);
-        double Ax, Ay, Bx, By;
-        point(o, 0, sa_, Ax, Ay);
-        point(o, 0, sb_, Bx, By);
+        // the chosen segment, selected with compile-time indices (no scratch)
+        const int fo = o0 + (pick >> 1);
+        int sa_ = 0, sb_ = 0;
+        double Ax = 0.0, Ay = 0.0, Bx = 0.0, By = 0.0;
+        T kp = T(0);
+#pragma unroll
+        for (int c0 = 0; c0 < 6; ++c0) {
+            if (c0 != pick) continue;
+            const int pk = pairs(o0 + (c0 >> 1), 0);
+            sa_ = side_a(pk, c0 & 1);
+            sb_ = side_b(pk, c0 & 1);
+            pt(c0 >> 1, sa_, Ax, Ay);
+            pt(c0 >> 1, sb_, Bx, By);
+            kp = key[c0];
+        }
         int s2, s3;
         double P2x, P2y, P3x, P3y;
         if (0.0 <= Ax) { s2 = sb_; s3 = sa_; P2x = Bx; P2y = By; P3x = Ax; P3y = Ay; }
         else { s2 = sa_; s3 = sb_; P2x = Ax; P2y = Ay; P3x = Bx; P3y = By; }
         double P1x, P1y, P4x, P4y;
-        neighbour(o, 0, s2, P1x, P1y);
-        neighbour(o, 0, s3, P4x, P4y);
-        return fit_height<T>((T)P1x, (T)P1y, (T)P2x, (T)P2y, (T)P3x, (T)P3y, (T)P4x, (T)P4y, key[pick]);
-    }
-
-    // Colour at the centre of face Q(0,0) relative to the advected polyline:
-    // start from the new colour of node (0,0), flip for aligned markers landing
-    // in [0, 1/2) on the bottom line and for advected segments crossing
-    // X = 1/2 below Y = 1/2.
-    __device__ int face_colour(int c00) const
-    {
-        int par = c00;
-#pragma unroll
-        for (int o = -1; o <= 1; ++o) {
-            if (!hhas(o, 0)) continue;
-            double X = (double)o + acc.xd(o, 0);
-            if (0.0 <= X && X < 0.5) par ^= 1;
-        }
-#pragma unroll
-        for (int o = -1; o <= 1; ++o) {
-            int pk = pairs(o, 0);
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                if (t >= nseg(pk)) break;
-                double Ax, Ay, Bx, By;
-                point(o, 0, side_a(pk, t), Ax, Ay);
-                point(o, 0, side_b(pk, t), Bx, By);
-                bool sa = 0.5 <= Ax, sb = 0.5 <= Bx;
-                if (sa == sb) continue;
-                T y = sa ? line_cross<T>(T(0.5), (T)Bx, (T)By, (T)Ax, (T)Ay)
-                         : line_cross<T>(T(0.5), (T)Ax, (T)Ay, (T)Bx, (T)By);
-                if (y < T(0.5)) par ^= 1;
-            }
-        }
-        return par;
+        int n1i, n1j, n1s, n4i, n4j, n4s;
+        neighbour(fo, 0, s2, n1i, n1j, n1s);
+        neighbour(fo, 0, s3, n4i, n4j, n4s);
+        two_points(n1i, n1j, n1s, n4i, n4j, n4s, P1x, P1y, P4x, P4y);
+        return fit_height<T>((T)P1x, (T)P1y, (T)P2x, (T)P2y, (T)P3x, (T)P3y, (T)P4x, (T)P4y, kp);
     }
 };
 

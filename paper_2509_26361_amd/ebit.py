@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libebit.so")
 
 EBIT_OK, EBIT_EINVAL, EBIT_ECFL, EBIT_ESTATE, EBIT_EHIP, EBIT_ENOSURR, EBIT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 EBIT_FP64, EBIT_FP32 = 0, 1
-EBIT_OPT_FULL_GRID = 1
+EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING = 1, 2
 
 _lib = None
 
@@ -36,6 +36,11 @@ class Desc(ctypes.Structure):
         ("scratch", ctypes.c_void_p),
         ("scratch_bytes", ctypes.c_size_t),
     ]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("sweep_ms", ctypes.c_double),
+                ("f2v", ctypes.c_int64), ("f2v_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -101,6 +106,11 @@ def lib():
         L.ebit_set_surrogate.restype = ctypes.c_int
         L.ebit_surrogate_dataset.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
         L.ebit_surrogate_dataset.restype = ctypes.c_int
+        L.ebit_advance.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_double, P, P]
+        L.ebit_advance.restype = ctypes.c_int
+        L.ebit_timing.argtypes = [P, ctypes.POINTER(Timing)]
+        L.ebit_timing.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -201,6 +211,24 @@ class Ebit:
     def step(self, Uxyz, g: float, dt: float, order=(0, 1, 2), stream=None):
         for d in order:
             self.sweep(d, Uxyz[d], g, dt, stream)
+
+    def advance(self, Uxyz, g, dt: float, C=None, stream=None):
+        """len(g) steps (sweeps x, y, z with time factor g[k], then Front2VOF
+        into C unless None), launched by the library."""
+        gs = (ctypes.c_double * max(1, len(g)))(*[float(v) for v in g])
+        U = (ctypes.c_void_p * 3)(*[_ptr(u) for u in Uxyz])
+        rc = lib().ebit_advance(self.ctx, len(g), U, gs, float(dt), _ptr(C) if C is not None else None,
+                                _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_advance")
+
+    def timing(self):
+        """Launch times recorded since the last call (EBIT_OPT_TIMING on)."""
+        t = Timing()
+        rc = lib().ebit_timing(self.ctx, ctypes.byref(t))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_timing")
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
 
     def front2vof(self, C, stream=None):
         rc = lib().ebit_front2vof(self.ctx, _ptr(C), _stream(stream))

@@ -236,3 +236,38 @@ def test_courant_violation_is_reported():
     with pytest.raises(E.EbitError) as ex:
         e.stats(C)
     assert ex.value.code == E.EBIT_ECFL
+
+
+def test_advance_equals_single_calls_and_timing():
+    """ebit_advance = the same sweeps and Front2VOF issued one call at a time
+    (bit-exact), and the timing option counts every launch."""
+    n = 32
+    sh = I.sphere_shape(n, centre=(0.45, 0.5, 0.55), R=0.2)
+    U = [T(u) for u in I.deformation_velocity(n)]
+    dt = 0.5 / n
+    gs = [I.deformation_time_factor(k * dt, 3.0) for k in range(12)]
+    runs = []
+    for mode in ("calls", "advance"):
+        e = E.Ebit(n, "fp64", dev())
+        e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        if mode == "calls":
+            for g in gs:
+                e.step(U, g, dt)
+                e.front2vof(C)
+        else:
+            e.set_option(E.EBIT_OPT_TIMING, 1)
+            e.advance(U, gs, dt, C)
+            tm = e.timing()
+            assert tm["sweeps"] == 3 * len(gs) and tm["f2v"] == len(gs)
+            assert tm["sweep_ms"] > 0 and tm["f2v_ms"] > 0
+            assert e.timing()["sweeps"] == 0
+        torch.cuda.synchronize()
+        fl, s = e.state()
+        runs.append((fl.cpu().numpy(), [x.cpu().numpy() for x in s], C.cpu().numpy(), e.stats(C)))
+    (f0, s0, c0, st0), (f1, s1, c1, st1) = runs
+    assert np.array_equal(f0, f1)
+    for k in range(3):
+        assert np.array_equal(s0[k], s1[k])
+    assert np.array_equal(c0, c1)
+    assert st0["n_interfacial_sum"] == st1["n_interfacial_sum"]
