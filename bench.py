@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--surr-rows", type=int, default=2_000_000, help="training rows (unambiguous cells)")
     p.add_argument("--surr-steps", type=int, default=20000, help="Adam steps")
     p.add_argument("--surr-batch", type=int, default=8192)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device copy of MIB MiB (float32 read + write), for scaling "
+                        "memory-traffic counters, and exit")
     return p.parse_args()
 
 
@@ -101,6 +104,16 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
+    if a.copy_calibration:
+        nel = a.copy_calibration * (1 << 20) // 4
+        x = torch.ones(nel, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nel * 4, "bytes_written": nel * 4,
+                                               "kernel": "elementwise multiply by 1 (3 launches)"}}))
+        return
     from paper_2509_26361_amd import ebit as E
     from paper_2509_26361_amd import inputs as I
 

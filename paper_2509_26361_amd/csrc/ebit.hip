@@ -59,6 +59,10 @@ constexpr int kTaskCap = 512;     // sweep: queued tasks per wave
 constexpr int kSlotCap = 128;     // sweep: queued face nodes per wave
 constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
 constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
+#ifndef EBIT_BATCH
+#define EBIT_BATCH 2
+#endif
+constexpr int kBatch = EBIT_BATCH;   // sweep: bricks staged together
 
 // totals reduced from the per-wave counters
 enum {
@@ -388,9 +392,9 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
             p.n = n;
             p.ci = P[D];
             p.cj = second ? P[A2] : P[A1];
-            p.strD = str[D];
-            p.strA = second ? str[A2] : str[A1];
-            p.base = second ? (long)P[A1] * str[A1] : (long)P[A2] * str[A2];
+            p.strD = (uint32_t)str[D];
+            p.strA = (uint32_t)(second ? str[A2] : str[A1]);
+            p.base = (uint32_t)(second ? (long)P[A1] * str[A1] : (long)P[A2] * str[A2]);
             p.hb = 4 + D;
             p.vb = second ? 4 + A2 : 4 + A1;
             p.fb = second ? 1 + A1 : 1 + A2;
@@ -418,8 +422,8 @@ template <typename T, int D>
 __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
-    __shared__ uint8_t tfl[kATile];
-    __shared__ double txd[kATile];
+    __shared__ uint8_t tfl[kBatch][kATile];
+    __shared__ double txd[kBatch][kATile];
     __shared__ uint32_t tq[kTaskCap];
     __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
@@ -441,6 +445,26 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
     ext[D] = kAD; ext[A1] = kAA; ext[A2] = kAA;
     lo[D] = -1; lo[A1] = 0; lo[A2] = 0;
 
+    // tile coordinates of the lane's staging entries kk = lane + 64 r (lane constants),
+    // packed: offset along x | y << 4 | z << 8 | LDS index << 12
+    constexpr int kR = (kATile + 63) / 64;
+    uint32_t tpk[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int kk = lane + 64 * r;
+        const int kc = kk < kATile ? kk : kATile - 1;
+        const int kt[3] = {kc % ext[0], (kc / ext[0]) % ext[1], kc / (ext[0] * ext[1])};
+        const int ti = kt[D] + kAD * (kt[A1] + kAA * kt[A2]);
+        tpk[r] = (uint32_t)(kt[0] | (kt[1] << 4) | (kt[2] << 8) | (ti << 12));
+    }
+    const uint32_t un = (uint32_t)n, unn = (uint32_t)a.g.nn;
+    auto tnode = [&](const int org[3], uint32_t pk, int &gpd) -> uint32_t {
+        int gp[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) gp[e] = wrp(org[e] + lo[e] + (int)((pk >> (4 * e)) & 15u), n);
+        gpd = gp[D];
+        return (uint32_t)gp[0] + __umul24((uint32_t)gp[1], un) + __umul24((uint32_t)gp[2], unn);
+    };
     Items it;
     if (a.full) {
         it.total = (uint32_t)nb;
@@ -474,100 +498,140 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
         }
         unsigned long long pend = __ballot(bl >= 0);
         while (pend) {
-            const int src = __ffsll((long long)pend) - 1;
-            pend &= pend - 1;
-            const int b = __shfl(bl, src);
+            // a batch of up to kBatch bricks, staged together: all flag loads,
+            // then all marker loads (D-edge markers of the tiles, and the
+            // unaligned markers stored at the lane's own nodes, for the Courant
+            // check), then the Euler step (eq. Eq_marker_dis) into the tiles
+            int bb[kBatch];
+            int nbat = 0;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                bb[j] = -1;
+                if (pend) {
+                    const int src = __ffsll((long long)pend) - 1;
+                    pend &= pend - 1;
+                    bb[j] = __builtin_amdgcn_readfirstlane(__shfl(bl, src));
+                    ++nbat;
+                }
+            }
+            if (nm + kBatch > kClaimCap || nc + kBatch > kClaimCap) claims();
+            int cfl = 0;
+            uint8_t fr[kBatch][kR], fown[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                fown[j] = 0;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) fr[j][r] = 0;
+                if (j >= nbat) continue;
+                const int b = bb[j];
+                const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+                fown[j] = a.fl[(uint32_t)(org[0] + lu[0]) + __umul24((uint32_t)(org[1] + lu[1]), un) +
+                               __umul24((uint32_t)(org[2] + lu[2]), unn)];
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    int gpd;
+                    fr[j][r] = a.fl[tnode(org, tpk[r], gpd)];
+                }
+            }
+            T sD[kBatch][kR], U0[kBatch][kR], UD[kBatch][kR];
+            T sAo[kBatch][2], UAo[kBatch][2], Uown[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+#pragma unroll
+                for (int r = 0; r < kR; ++r) sD[j][r] = U0[j][r] = UD[j][r] = T(0);
+                sAo[j][0] = sAo[j][1] = UAo[j][0] = UAo[j][1] = Uown[j] = T(0);
+                if (j >= nbat) continue;
+                const int b = bb[j];
+                const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    if ((fr[j][r] >> (4 + D)) & 1) {
+                        int gpd;
+                        const uint32_t q = tnode(org, tpk[r], gpd);
+                        sD[j][r] = a.s[D][q];
+                        U0[j][r] = a.U[q];
+                        UD[j][r] = a.U[gpd + 1 == n ? q - (uint32_t)(n - 1) * (uint32_t)str[D] : q + (uint32_t)str[D]];
+                    }
+                }
+                const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
+                if (fown[j] & ((1u << (4 + A1)) | (1u << (4 + A2)))) Uown[j] = a.U[qs];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int A = e == 0 ? A1 : A2;
+                    if ((fown[j] >> (4 + A)) & 1) {
+                        const long q1 = org[A] + lu[A] + 1 == n ? qs - (long)(n - 1) * str[A] : qs + str[A];
+                        sAo[j][e] = a.s[A][qs];
+                        UAo[j][e] = a.U[q1];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                if (j >= nbat) continue;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    const int kk = lane + 64 * r;
+                    if (kk >= kATile) continue;
+                    const int kt[3] = {(int)(tpk[r] & 15u), (int)((tpk[r] >> 4) & 15u), (int)((tpk[r] >> 8) & 15u)};
+                    const int ti = (int)(tpk[r] >> 12);
+                    double xd = 0.0;
+                    if ((fr[j][r] >> (4 + D)) & 1) {
+                        T u = U0[j][r] + sD[j][r] * (UD[j][r] - U0[j][r]);
+                        T del = a.c * u;
+                        xd = (double)sD[j][r] + (double)del;
+                        const bool own = kt[D] >= 1 && kt[D] < 5 && kt[A1] < 4 && kt[A2] < 4;
+                        if (own && fabs((double)del) > 1.0) ++cfl;
+                    }
+                    tfl[j][ti] = fr[j][r];
+                    txd[j][ti] = xd;
+                }
+                // Courant check of the unaligned markers stored at this node
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int A = e == 0 ? A1 : A2;
+                    if ((fown[j] >> (4 + A)) & 1) {
+                        T del = a.c * (Uown[j] + sAo[j][e] * (UAo[j][e] - Uown[j]));
+                        if (fabs((double)del) > 1.0) ++cfl;
+                    }
+                }
+            }
+            __syncthreads();
+            // new colours of the tile nodes whose D-predecessor is in the tile
+            for (int kk = lane; kk < nbat * kATile; kk += 64) {
+                const int j = kk / kATile, k0 = kk - j * kATile;
+                if (k0 % kAD == 0) continue;
+                uint8_t f = tfl[j][k0], fm = tfl[j][k0 - 1];
+                int c = f & 1;
+                if (((fm >> (4 + D)) & 1) && txd[j][k0 - 1] >= 1.0) c ^= 1;
+                if (((f >> (4 + D)) & 1) && txd[j][k0] < 0.0) c ^= 1;
+                tfl[j][k0] = (uint8_t)((f & 0x7f) | (c << 7));
+            }
+            __syncthreads();
+            for (int j = 0; j < nbat; ++j) {
+            int b = bb[0];
+#pragma unroll
+            for (int u = 1; u < kBatch; ++u)
+                if (j == u) b = bb[u];
             if (ntask + 4 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
                 run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
                 nslot = 0;
             }
-            if (nm == kClaimCap || nc == kClaimCap) claims();
             ++nact;
             const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
             const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
-            int cfl = 0;
-            // stage flags and the Euler step (eq. Eq_marker_dis) of D-edge markers;
-            // all flag loads first, then all marker loads (with those of the
-            // unaligned markers stored at the lane's own node, for the Courant check)
-            const uint8_t fown = a.fl[qs];
-            constexpr int kR = (kATile + 63) / 64;
-            long qr[kR];
-            uint8_t fr[kR];
-            int gpd[kR];
-    #pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                int kk = lane + 64 * r;
-                int kc = kk < kATile ? kk : kATile - 1;
-                int kt[3] = {kc % ext[0], (kc / ext[0]) % ext[1], kc / (ext[0] * ext[1])};
-                int gp[3];
-    #pragma unroll
-                for (int e = 0; e < 3; ++e) gp[e] = wrp(org[e] + lo[e] + kt[e], n);
-                qr[r] = gp[0] + str[1] * gp[1] + str[2] * gp[2];
-                gpd[r] = gp[D];
-                fr[r] = a.fl[qr[r]];
-            }
-            T sD[kR], U0[kR], UD[kR];
-    #pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                sD[r] = U0[r] = UD[r] = T(0);
-                if ((fr[r] >> (4 + D)) & 1) {
-                    const long q = qr[r];
-                    sD[r] = a.s[D][q];
-                    U0[r] = a.U[q];
-                    UD[r] = a.U[gpd[r] + 1 == n ? q - (long)(n - 1) * str[D] : q + str[D]];
-                }
-            }
-            T sAo[2], UAo[2], Uown = T(0);
-            if (fown & ((1u << (4 + A1)) | (1u << (4 + A2)))) Uown = a.U[qs];
-    #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int A = e == 0 ? A1 : A2;
-                sAo[e] = UAo[e] = T(0);
-                if ((fown >> (4 + A)) & 1) {
-                    const long q1 = org[A] + lu[A] + 1 == n ? qs - (long)(n - 1) * str[A] : qs + str[A];
-                    sAo[e] = a.s[A][qs];
-                    UAo[e] = a.U[q1];
-                }
-            }
-    #pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                int kk = lane + 64 * r;
-                if (kk >= kATile) continue;
-                int kt[3] = {kk % ext[0], (kk / ext[0]) % ext[1], kk / (ext[0] * ext[1])};
-                int ti = kt[D] + kAD * (kt[A1] + kAA * kt[A2]);
-                double xd = 0.0;
-                if ((fr[r] >> (4 + D)) & 1) {
-                    T u = U0[r] + sD[r] * (UD[r] - U0[r]);
-                    T del = a.c * u;
-                    xd = (double)sD[r] + (double)del;
-                    const bool own = kt[D] >= 1 && kt[D] < 5 && kt[A1] < 4 && kt[A2] < 4;
-                    if (own && fabs((double)del) > 1.0) ++cfl;
-                }
-                tfl[ti] = fr[r];
-                txd[ti] = xd;
-            }
-            __syncthreads();
-            // new colours of the tile nodes whose D-predecessor is in the tile
-            for (int kk = lane; kk < kATile; kk += 64) {
-                if (kk % kAD == 0) continue;
-                uint8_t f = tfl[kk], fm = tfl[kk - 1];
-                int c = f & 1;
-                if (((fm >> (4 + D)) & 1) && txd[kk - 1] >= 1.0) c ^= 1;
-                if (((f >> (4 + D)) & 1) && txd[kk] < 0.0) c ^= 1;
-                tfl[kk] = (uint8_t)((f & 0x7f) | (c << 7));
-            }
-            __syncthreads();
-            auto ncol = [&](int di, int d1, int d2) { return (tfl[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
-            const uint8_t fself = tfl[tself];
+            const uint8_t *tf = tfl[j];
+            const double *tx = txd[j];
+            auto ncol = [&](int di, int d1, int d2) { return (tf[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
+            const uint8_t fself = tf[tself];
             const int c00 = ncol(0, 0, 0), c10 = ncol(1, 0, 0);
             uint8_t out = (uint8_t)c00;
             T sdn = T(0);
             int fb = 0, merged = 0;
             {
-                uint8_t fm = tfl[tself - 1], fp = tfl[tself + 1];
+                uint8_t fm = tf[tself - 1], fp = tf[tself + 1];
                 bool hm = (fm >> (4 + D)) & 1, h0 = (fself >> (4 + D)) & 1, hp = (fp >> (4 + D)) & 1;
-                double xm = txd[tself - 1], x0 = txd[tself], xp = txd[tself + 1];
+                double xm = tx[tself - 1], x0 = tx[tself], xp = tx[tself + 1];
                 bool lm = hm && xm >= 1.0, l0 = h0 && x0 >= 0.0 && x0 < 1.0, lp = hp && xp < 0.0;
                 int kl = (int)lm + (int)l0 + (int)lp;
                 if (c00 != c10) {
@@ -589,15 +653,6 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                 }
             }
             out |= (uint8_t)(fself & (1u << (1 + D)));   // faces normal to D keep their colour
-            // Courant check of the unaligned markers stored at this node
-    #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int A = e == 0 ? A1 : A2;
-                if ((fown >> (4 + A)) & 1) {
-                    T del = a.c * (Uown + sAo[e] * (UAo[e] - Uown));
-                    if (fabs((double)del) > 1.0) ++cfl;
-                }
-            }
             bool task[4];
             {
                 const int c01 = ncol(0, 1, 0), c11 = ncol(1, 1, 0);   // plane (D, A1)
@@ -651,9 +706,10 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             nm += hasm ? 1 : 0;
             nc += (hasm || chg) ? 1 : 0;
             fbc += fb;
-            cflc += cfl;
             mergedc += merged;
-            __syncthreads();   // the tile is reused by the next brick
+            }
+            cflc += cfl;
+            __syncthreads();   // the tiles are reused by the next batch
         }
     }
     run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
@@ -920,19 +976,33 @@ struct F2VArgs {
     int full;
 };
 
-// load the 8 corner flag bytes of cell q (corner k = ox + 2 oy + 4 oz)
-__device__ __forceinline__ void corner_index(int n, long nn, long q, long qc[8])
+// node indices of the 8 corners of cell (x, y, z) (corner k = ox + 2 oy + 4 oz)
+__device__ __forceinline__ void corner_index(int n, long nn, int x, int y, int z, uint32_t qc[8])
 {
-    const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / nn);
-    const int x1 = x + 1 == n ? 0 : x + 1, y1 = y + 1 == n ? 0 : y + 1, z1 = z + 1 == n ? 0 : z + 1;
-    qc[0] = x + (long)n * y + nn * z;
-    qc[1] = x1 + (long)n * y + nn * z;
-    qc[2] = x + (long)n * y1 + nn * z;
-    qc[3] = x1 + (long)n * y1 + nn * z;
-    qc[4] = x + (long)n * y + nn * z1;
-    qc[5] = x1 + (long)n * y + nn * z1;
-    qc[6] = x + (long)n * y1 + nn * z1;
-    qc[7] = x1 + (long)n * y1 + nn * z1;
+    const uint32_t un = (uint32_t)n, unn = (uint32_t)nn;
+    const uint32_t x0 = (uint32_t)x, x1 = x + 1 == n ? 0u : (uint32_t)x + 1u;
+    const uint32_t y0 = __umul24((uint32_t)y, un), y1 = __umul24(y + 1 == n ? 0u : (uint32_t)y + 1u, un);
+    const uint32_t z0 = __umul24((uint32_t)z, unn), z1 = __umul24(z + 1 == n ? 0u : (uint32_t)z + 1u, unn);
+    qc[0] = x0 + y0 + z0;
+    qc[1] = x1 + y0 + z0;
+    qc[2] = x0 + y1 + z0;
+    qc[3] = x1 + y1 + z0;
+    qc[4] = x0 + y0 + z1;
+    qc[5] = x1 + y0 + z1;
+    qc[6] = x0 + y1 + z1;
+    qc[7] = x1 + y1 + z1;
+}
+
+// cell coordinates packed in 30 bits (n <= 1024) and back
+__device__ __forceinline__ uint32_t pack_xyz(int x, int y, int z)
+{
+    return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+}
+__device__ __forceinline__ void unpack_xyz(uint32_t p, int &x, int &y, int &z)
+{
+    x = (int)(p & 1023u);
+    y = (int)((p >> 10) & 1023u);
+    z = (int)(p >> 20);
 }
 
 // 12-bit marker mask of a cell; edge id 4e + oA + 2 oB starts at the corner
@@ -966,13 +1036,15 @@ __device__ __forceinline__ int f2v_cells(const F2VArgs<T> &a, const uint32_t *cq
     const int lane = threadIdx.x & 63;
     int amb = 0;
     if (lane < cnt) {
-        const long q = cq[lane];
+        int x, y, z;
+        unpack_xyz(cq[lane], x, y, z);
         const uint64_t pk = cf[lane];
         uint8_t f[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) f[k] = (uint8_t)(pk >> (8 * k));
-        long qc[8];
-        corner_index(a.g.n, a.g.nn, q, qc);
+        uint32_t qc[8];
+        corner_index(a.g.n, a.g.nn, x, y, z, qc);
+        const uint32_t q = qc[0];
         const int has = marker_mask(f);
         T sv[12];
 #pragma unroll
@@ -1027,9 +1099,9 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
             const int b = __shfl(bl, src);
             const int x = (b % nb1) * 4 + (lane & 3), y = ((b / nb1) % nb1) * 4 + ((lane >> 2) & 3),
                       z = (b / (nb1 * nb1)) * 4 + (lane >> 4);
-            const long q = x + (long)n * y + nn * z;
-            long qc[8];
-            corner_index(n, nn, q, qc);
+            uint32_t qc[8];
+            corner_index(n, nn, x, y, z, qc);
+            const uint32_t q = qc[0];
             uint8_t f[8];
     #pragma unroll
             for (int kk = 0; kk < 8; ++kk) f[kk] = a.fl[qc[kk]];
@@ -1041,7 +1113,7 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
                 uint64_t pk = 0;
     #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) pk |= (uint64_t)f[kk] << (8 * kk);
-                cq[nq + r] = (uint32_t)q;
+                cq[nq + r] = pack_xyz(x, y, z);
                 cf[nq + r] = pk;
                 if (np + r < a.g.segcap) seg[np + r] = (uint32_t)q;
             }
@@ -1126,8 +1198,9 @@ __device__ __forceinline__ int cell_ambiguous(const uint8_t f[8], int has)
 template <typename T>
 __device__ __forceinline__ int load_cell(const F2VArgs<T> &a, long q, uint8_t f[8], T sv[12])
 {
-    long qc[8];
-    corner_index(a.g.n, a.g.nn, q, qc);
+    const int n = a.g.n;
+    uint32_t qc[8];
+    corner_index(n, a.g.nn, (int)(q % n), (int)((q / n) % n), (int)(q / a.g.nn), qc);
 #pragma unroll
     for (int k = 0; k < 8; ++k) f[k] = a.fl[qc[k]];
     const int has = marker_mask(f);

@@ -111,23 +111,28 @@ struct PlaneTask {
     T c;                          // (dt n) g
     int n;
     int ci, cj;                   // the node's coordinates along D and A
-    long strD, strA, base;        // index strides of D and A; offset of the B coordinate
+    uint32_t strD, strA, base;    // index strides of D and A; offset of the B coordinate (n <= 1024)
     int hb, vb, fb;               // flag bits: H marker, V marker, colour of Q(i,j)
+    uint32_t xo[6], yo[4];        // index offsets of i = -3..2 along D and of j = -1..2 along A (+ base)
     // bits of the flags of offsets i = -3..2, j = -1..2 at bit (i + 3) + 6 (j + 1):
     uint32_t mH, mV, mF, mC;      // H marker, V marker, colour of Q(i,j), node colour
 
-    __device__ __forceinline__ long node(int i, int j) const
+    __device__ __forceinline__ uint32_t node(int i, int j) const
     {
-        return (long)wrp(ci + i, n) * strD + (long)wrp(cj + j, n) * strA + base;
+        return __umul24((uint32_t)wrp(ci + i, n), strD) + __umul24((uint32_t)wrp(cj + j, n), strA) + base;
     }
     static __device__ __forceinline__ int bit(int i, int j) { return (i + 3) + 6 * (j + 1); }
     __device__ __forceinline__ void fetch_flags()
     {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) xo[i] = __umul24((uint32_t)wrp(ci + i - 3, n), strD);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) yo[j] = __umul24((uint32_t)wrp(cj + j - 1, n), strA) + base;
         uint32_t b[24];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int i = 0; i < 6; ++i) b[i + 6 * j] = fl[node(i - 3, j - 1)];
+            for (int i = 0; i < 6; ++i) b[i + 6 * j] = fl[xo[i] + yo[j]];
         mH = mV = mF = mC = 0;
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
@@ -184,7 +189,8 @@ struct PlaneTask {
     // where the marker of a side of Q(fi,fj) is stored: fraction array, its
     // node, the node across the edge (for the velocity), and the point's
     // integer offsets
-    __device__ __forceinline__ void locate(int fi, int fj, int side, bool &hz, long &q, long &q1, int &xi, int &yj) const
+    __device__ __forceinline__ void locate(int fi, int fj, int side, bool &hz, uint32_t &q, uint32_t &q1, int &xi,
+                                           int &yj) const
     {
         hz = side == 0 || side == 2;
         xi = side == 1 ? fi + 1 : fi;
@@ -197,7 +203,7 @@ struct PlaneTask {
                                               double &Xb, double &Yb) const
     {
         bool ha, hb;
-        long qa, qa1, qb, qb1;
+        uint32_t qa, qa1, qb, qb1;
         int xa, ya, xb, yb;
         locate(fa, fja, sa, ha, qa, qa1, xa, ya);
         locate(fb, fjb, sb, hb, qb, qb1, xb, yb);
@@ -226,11 +232,11 @@ struct PlaneTask {
         // the node): the velocities at nodes (o0+k, r), k = 0..3, r = 0, 1 serve
         // both edge families; every load is issued before any arithmetic (a
         // missing marker reads a valid entry and is masked)
-        long qn[4][2];
+        uint32_t qn[4][2];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) qn[k][r] = node(o0 + k, r);
+            for (int r = 0; r < 2; ++r) qn[k][r] = (face ? xo[k + 2] : xo[k + 1]) + yo[r + 1];
         T Un[4][2], sh_[3][2], sv_[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
