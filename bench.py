@@ -53,13 +53,41 @@ def parse():
     p.add_argument("--surr-rows", type=int, default=2_000_000, help="training rows (unambiguous cells)")
     p.add_argument("--surr-steps", type=int, default=20000, help="Adam steps")
     p.add_argument("--surr-batch", type=int, default=8192)
+    p.add_argument("--timing-every", type=int, default=8,
+                   help="bracket every k-th launch of each kernel with HIP events (the roofline's duration)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB (float32 read + write), for scaling "
                         "memory-traffic counters, and exit")
     return p.parse_args()
 
 
-def run_case(E, I, torch, n, precision, W, K, events, theta=None):
+def kernel_source_hash():
+    """sha256 of the hot-path kernel sources: a stored traffic figure applies
+    only to the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ebit.hip", "ebit_device.h"):
+        with open(os.path.join(ROOT, "paper_2509_26361_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, n, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
+    none for this workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_deformation_{n}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_hash()
+    for line in open(path):
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "sha256":
+            return float(f[2]) if f[4] == sha else None
+    return None
+
+
+def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8):
     """W untimed steps, then K timed steps of the deformation workload
     (Front2VOF through the learned surrogate when `theta` is given)."""
     T_end = 3.0
@@ -81,7 +109,7 @@ def run_case(E, I, torch, n, precision, W, K, events, theta=None):
     gvals = [I.deformation_time_factor(k * dt, T_end) for k in range(W + K)]
     e.advance(Ud, gvals[:W], dt, C)
     st0 = e.stats(C)
-    e.set_option(E.EBIT_OPT_TIMING, 1 if events else 0)
+    e.set_option(E.EBIT_OPT_TIMING, every if events else 0)
     e.timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,7 +151,7 @@ def main():
     K = a.steps if a.steps is not None else period - a.warmup
     W = a.warmup
     print(f"[bench] deformation n={n} precision={a.precision} warmup={W} steps={K}", file=sys.stderr, flush=True)
-    r = run_case(E, I, torch, n, a.precision, W, K, events=True)
+    r = run_case(E, I, torch, n, a.precision, W, K, events=True, every=a.timing_every)
     wall, n_start, st0, st1, kt = r["wall"], r["n_start"], r["st0"], r["st1"], r["kt"]
     value = n_start / wall
     tot = {k: v[1] for k, v in kt.items()}
@@ -157,12 +185,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": stored_traffic("k_sweep" if dom == "sweep" else "k_f2v", n, a.precision),
             "bytes_per_unit": BYTES[a.precision][dom],
             "units_per_launch": units_per_launch,
             "avg_launch_us": avg_dur * 1e6,
+            "timed_launches": kt[dom][0],
         },
-        "time_split_ms": {k: v * 1e3 for k, v in tot.items()},
+        "launch_us": {k: (kt[k][1] / kt[k][0] * 1e6 if kt[k][0] else None) for k in kt},
         "interfacial_cells": {"start": st0["n_interfacial"], "end": st1["n_interfacial"],
                               "mean": n_start / K},
         "volume": {"start": st0["volume"] + st0["volume_comp"], "end": st1["volume"] + st1["volume_comp"]},
@@ -257,14 +286,13 @@ def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
     fwd_s = s_ev.elapsed_time(e_ev) * 1e-3 / reps
     del Xt, ct, tr
     torch.cuda.empty_cache()
-    q = run_case(E, I, torch, n, "fp32", W, K, events=True, theta=theta)
+    q = run_case(E, I, torch, n, "fp32", W, K, events=True, theta=theta, every=a.timing_every)
     V = q["st1"]["volume"] + q["st1"]["volume_comp"]
     es = float((q["C"] - q["C0"]).abs().sum() / q["C0"].sum())
-    tot = {k: v[1] for k, v in q["kt"].items()}
     return {
         "value": q["n_start"] / q["wall"],
         "ms_per_step": q["wall"] / K * 1e3,
-        "f2v_ms_per_call": tot["f2v"] / K * 1e3,
+        "f2v_us_per_launch": (q["kt"]["f2v"][1] / q["kt"]["f2v"][0] * 1e6) if q["kt"]["f2v"][0] else None,
         "volume_rel_err_vs_fp64": abs(V - V64) / V64,
         "max_abs_C_diff_vs_fp64": float((q["C"] - C64).abs().max()),
         "e_shape_at_T": es if q["ended_at_T"] else None,

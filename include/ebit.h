@@ -160,12 +160,14 @@ int ebit_advance(ebit_ctx *ctx, int32_t nsteps, const void *const *U, const doub
 /* Option switches. */
 enum {
     EBIT_OPT_FULL_GRID = 1,   /* 1: process every cell, not only the band */
-    EBIT_OPT_TIMING = 2       /* 1: bracket each sweep / Front2VOF launch with HIP events on its stream */
+    EBIT_OPT_TIMING = 2       /* k > 0: bracket every k-th sweep launch and every k-th Front2VOF launch
+                                 with HIP events on its stream; 0: off */
 };
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
 
-/* Launch times recorded while EBIT_OPT_TIMING is on (at most 8192 launches
- * between two calls; later ones are not timed). */
+/* Launch times recorded while EBIT_OPT_TIMING is on (at most 8192 timed
+ * launches between two calls; later ones are not timed).  Each bracketed
+ * duration includes the launch's dispatch and completion on the stream. */
 typedef struct {
     int64_t sweeps;         /* timed ebit_advect_sweep launches */
     double sweep_ms;        /* their summed duration */

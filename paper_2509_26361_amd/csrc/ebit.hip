@@ -1447,7 +1447,9 @@ struct ebit_ctx {
     int full;              // process every brick
     const void *lastC;     // C array of the previous Front2VOF
     const float *surr;     // surrogate parameters (NULL: geometric Front2VOF only)
-    int timing;            // bracket launches with events
+    int timing;            // bracket every timing-th launch of each kind with events (0: off)
+    unsigned tseen[2];     // launches of each kind since timing was switched on
+    int tsel;              // the current launch is bracketed
     hipEvent_t *ev;        // 2 * kTimed events
     uint8_t *ev_kind;      // 0 sweep, 1 Front2VOF
     int ev_n;              // launches recorded since the last ebit_timing
@@ -1471,18 +1473,23 @@ int clampi(int v, int hi) { return v < hi ? (v > 0 ? v : 1) : hi; }
 
 constexpr int kTimed = 8192;   // launches timed between two ebit_timing calls
 
-bool timed(const ebit_ctx *c) { return c->timing && c->ev && c->ev_n < kTimed; }
-
-void time_begin(ebit_ctx *c, hipStream_t st)
+// every c->timing-th launch of each kind is bracketed (events perturb the
+// stream, so a sample of the launches keeps the timed run representative)
+void time_begin(ebit_ctx *c, hipStream_t st, int kind)
 {
-    if (timed(c)) (void)hipEventRecord(c->ev[2 * c->ev_n], st);
+    c->tsel = 0;
+    if (!c->timing || !c->ev || c->ev_n >= kTimed) return;
+    if (c->tseen[kind]++ % (unsigned)c->timing != 0) return;
+    c->tsel = 1;
+    (void)hipEventRecord(c->ev[2 * c->ev_n], st);
 }
 
 void time_end(ebit_ctx *c, hipStream_t st, int kind)
 {
-    if (!timed(c)) return;
+    if (!c->tsel) return;
     (void)hipEventRecord(c->ev[2 * c->ev_n + 1], st);
     c->ev_kind[c->ev_n++] = (uint8_t)kind;
+    c->tsel = 0;
 }
 
 template <typename T, int D>
@@ -1502,7 +1509,7 @@ void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
     a.t = c->t;
     a.fgen = c->fgen;
     a.full = c->full;
-    time_begin(c, st);
+    time_begin(c, st, 0);
     hipLaunchKernelGGL((k_sweep<T, D>), dim3(c->g.nw), dim3(64), 0, st, a);
     time_end(c, st, 0);
 }
@@ -1533,7 +1540,7 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     a.w = c->w;
     a.gen = c->fgen;
     a.full = full;
-    time_begin(c, st);
+    time_begin(c, st, 1);
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
         hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + 3) / 4, 256 * 2)), dim3(256), 0, st, a, c->surr);
@@ -1773,7 +1780,8 @@ int ebit_set_option(ebit_ctx *c, int option, int value)
             c->ev_kind = kind;
             c->ev_n = 0;
         }
-        c->timing = value != 0;
+        c->timing = value > 0 ? value : 0;
+        c->tseen[0] = c->tseen[1] = 0;
         return EBIT_OK;
     }
     return EBIT_EINVAL;

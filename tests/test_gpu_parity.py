@@ -271,3 +271,19 @@ def test_advance_equals_single_calls_and_timing():
         assert np.array_equal(s0[k], s1[k])
     assert np.array_equal(c0, c1)
     assert st0["n_interfacial_sum"] == st1["n_interfacial_sum"]
+
+
+def test_timing_samples_every_kth_launch():
+    n = 16
+    sh = I.sphere_shape(n, centre=(0.5, 0.5, 0.5), R=0.25)
+    U = [T(u) for u in I.deformation_velocity(n)]
+    e = E.Ebit(n, "fp64", dev())
+    e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+    C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    e.set_option(E.EBIT_OPT_TIMING, 4)
+    e.advance(U, [1.0] * 12, 0.5 / n, C)
+    tm = e.timing()
+    assert tm["sweeps"] == 9 and tm["f2v"] == 3      # launches 0, 4, 8, ... of each kind
+    e.set_option(E.EBIT_OPT_TIMING, 0)
+    e.advance(U, [1.0] * 2, 0.5 / n, C)
+    assert e.timing()["sweeps"] == 0
