@@ -100,6 +100,7 @@ struct Work {
     uint32_t *cm[3];     // cm[t % 3][b] == t <=> brick b is in the band list of sweep t
     uint32_t *fmark;     // fmark[b] == g <=> brick b is in the revisit list of Front2VOF generation g
     uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
+    uint32_t *bchg;      // last sweep at which brick b was not quiet (see k_sweep)
     uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of nb entries
     uint32_t *bnum;      // [4][kSub] sub-list lengths
     uint32_t *flist[2];  // revisit list of generation g: flist[g % 2]
@@ -126,6 +127,7 @@ size_t work_layout(int n, Work *w, char *base)
     for (int k = 0; k < 3; ++k) { p = take(nb * 4); if (w) w->cm[k] = (uint32_t *)p; }
     p = take(nb * 4); if (w) w->fmark = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bcnt = (uint32_t *)p;
+    p = take(nb * 4); if (w) w->bchg = (uint32_t *)p;
     for (int k = 0; k < 4; ++k) { p = take(kSub * nb * 4); if (w) w->blist[k] = (uint32_t *)p; }
     p = take(4 * kSub * 4); if (w) w->bnum = (uint32_t *)p;
     for (int k = 0; k < 2; ++k) { p = take(kSub * nb * 4); if (w) w->flist[k] = (uint32_t *)p; }
@@ -166,48 +168,69 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// Claims of list membership, batched per wave: the bricks at offsets
-// `per` = 27 (the 3x3x3 neighbourhood) or 8 (the brick and its lower
-// neighbours) of `nsrc` source bricks join the list whose membership is
-// `mark[b] == v`.  An atomic exchange of the mark decides the one claimant of
-// each brick, which appends it, wave-aggregated, to sub-list `sub`.  Four
-// claims per lane are in flight at a time.
-__device__ __forceinline__ void claim_batch(const int *src, int nsrc, int per, int nb1, uint32_t *mark, uint32_t v,
-                                            uint32_t *list, uint32_t *num, int sub, uint32_t cap)
+// Claims of list membership, batched per wave.  Two lists at once: the
+// bricks of the 3x3x3 neighbourhoods of `na` source bricks join list A
+// (membership markA[b] == vA) and the bricks at offsets (0 or -1 on each axis)
+// of `nbr` source bricks join list B.  An atomic exchange of the mark decides
+// the one claimant of each brick, which appends it, wave-aggregated, to
+// sub-list `sub` of its list.  Up to four claims per lane are in flight.
+struct ClaimList {
+    uint32_t *mark;
+    uint32_t v;
+    uint32_t *list;
+    uint32_t *num;
+};
+
+__device__ __forceinline__ void claim_two(const int *srcA, int na, const int *srcB, int nbr, int nb1, ClaimList A,
+                                          ClaimList B, int sub, uint32_t cap)
 {
     const int lane = threadIdx.x & 63;
-    const int total = nsrc * per;
+    const int ta = na * 27, total = ta + nbr * 8;
     for (int base = 0; base < total; base += 256) {
         int nbk[4];
-        bool take[4];
+        bool take[4], inA[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = base + 64 * u + lane;
             take[u] = false;
+            inA[u] = c < ta;
             nbk[u] = 0;
-            if (c < total) {
-                const int b = src[c / per], d = c % per;
-                nbk[u] = per == 27 ? brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1)
-                                   : brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
+            if (c < ta) {
+                const int b = srcA[c / 27], d = c % 27;
+                nbk[u] = brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1);
+            } else if (c < total) {
+                const int b = srcB[(c - ta) >> 3], d = (c - ta) & 7;
+                nbk[u] = brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (base + 64 * u + lane < total) take[u] = atomicExch(&mark[nbk[u]], v) != v;
-        unsigned long long bal[4];
-        int cnt = 0;
+        for (int u = 0; u < 4; ++u) {
+            if (base + 64 * u + lane >= total) continue;
+            const ClaimList &L = inA[u] ? A : B;
+            take[u] = atomicExch(&L.mark[nbk[u]], L.v) != L.v;
+        }
+        unsigned long long balA[4], balB[4];
+        int cA = 0, cB = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { bal[u] = __ballot(take[u]); cnt += __popcll(bal[u]); }
-        if (cnt == 0) continue;
-        uint32_t pos = 0;
-        if (lane == 0) pos = atomicAdd(&num[sub], (uint32_t)cnt);
-        pos = __shfl(pos, 0);
+        for (int u = 0; u < 4; ++u) {
+            balA[u] = __ballot(take[u] && inA[u]);
+            balB[u] = __ballot(take[u] && !inA[u]);
+            cA += __popcll(balA[u]);
+            cB += __popcll(balB[u]);
+        }
+        uint32_t pA = 0, pB = 0;
+        if (lane == 0 && cA) pA = atomicAdd(&A.num[sub], (uint32_t)cA);
+        if (lane == 0 && cB) pB = atomicAdd(&B.num[sub], (uint32_t)cB);
+        pA = __shfl(pA, 0);
+        pB = __shfl(pB, 0);
         const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint32_t p = pos + (uint32_t)__popcll(bal[u] & lt);
-            if (take[u] && p < cap) list[(size_t)sub * cap + p] = (uint32_t)nbk[u];
-            pos += (uint32_t)__popcll(bal[u]);
+            const uint32_t qa = pA + (uint32_t)__popcll(balA[u] & lt), qb = pB + (uint32_t)__popcll(balB[u] & lt);
+            if (take[u] && inA[u] && qa < cap) A.list[(size_t)sub * cap + qa] = (uint32_t)nbk[u];
+            if (take[u] && !inA[u] && qb < cap) B.list[(size_t)sub * cap + qb] = (uint32_t)nbk[u];
+            pA += (uint32_t)__popcll(balA[u]);
+            pB += (uint32_t)__popcll(balB[u]);
         }
     }
 }
@@ -312,7 +335,10 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         int x = bx * 4 + (lane & 3), y = by * 4 + ((lane >> 2) & 3), z = bz * 4 + (lane >> 4);
         long q = x + (long)g.n * y + g.nn * z;
         const bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
-        if (hasm) claim_batch(&b, 1, 27, g.nb1, w.cm[2], 2u, w.blist[2], w.bnum + 2 * kSub, blockIdx.x % kSub, (uint32_t)g.nb);
+        if (hasm) {
+            const ClaimList A{w.cm[2], 2u, w.blist[2], w.bnum + 2 * kSub};
+            claim_two(&b, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.nb);
+        }
     }
 }
 
@@ -326,6 +352,7 @@ __global__ void k_zero_work(Work w, Geo g)
         w.cm[2][i] = 0;
         w.fmark[i] = 0;
         w.bcnt[i] = 0;
+        w.bchg[i] = 0;
     }
     if (i < 4 * kSub) w.bnum[i] = 0;
     if (i < 2 * kSub) w.fnum[i] = 0;
@@ -477,13 +504,15 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
     auto claims = [&]() {
         __syncthreads();
-        claim_batch(mbr, nm, 27, nb1, cm_next, t + 1, lnext, nnext, sub, (uint32_t)nb);
-        claim_batch(cbr, nc, 8, nb1, a.w.fmark, a.fgen, lrev, nrev, sub, (uint32_t)nb);
+        claim_two(mbr, nm, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
+                  ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)nb);
         __syncthreads();
         nm = 0;
         nc = 0;
     };
-    // this wave's items k = wv + i nw, resolved 64 at a time (one per lane)
+    // this wave's items k = wv + i nw, resolved one per lane (a static
+    // schedule: a shared counter handing out items cost more than the
+    // imbalance it removes)
     const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
     for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
         int bl = -1;
@@ -517,9 +546,12 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             if (nm + kBatch > kClaimCap || nc + kBatch > kClaimCap) claims();
             int cfl = 0;
             uint8_t fr[kBatch][kR], fown[kBatch];
+            uint32_t lastchg[kBatch];
+            bool quiet[kBatch];
 #pragma unroll
             for (int j = 0; j < kBatch; ++j) {
                 fown[j] = 0;
+                lastchg[j] = 0;
 #pragma unroll
                 for (int r = 0; r < kR; ++r) fr[j][r] = 0;
                 if (j >= nbat) continue;
@@ -532,6 +564,25 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                     int gpd;
                     fr[j][r] = a.fl[tnode(org, tpk[r], gpd)];
                 }
+                lastchg[j] = a.w.bchg[b];
+            }
+            // A brick whose tile (halo included) holds no marker, and whose
+            // faces containing D already carry their nodes' colour, is left
+            // unchanged by the sweep (a consistent state has uniform colours
+            // there; only faces normal to D may keep another colour); if it
+            // was also unchanged by the previous sweep, both buffers already
+            // hold it and it needs no work at all.
+            bool skip[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                bool anym = false;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    const uint32_t f = fr[j][r];
+                    anym |= (f & 0x70) != 0 || (((f >> (1 + A1)) ^ f) & 1) != 0 || (((f >> (1 + A2)) ^ f) & 1) != 0;
+                }
+                quiet[j] = j < nbat && __ballot(anym) == 0;
+                skip[j] = quiet[j] && !a.full && lastchg[j] + 2 <= t;
             }
             T sD[kBatch][kR], U0[kBatch][kR], UD[kBatch][kR];
             T sAo[kBatch][2], UAo[kBatch][2], Uown[kBatch];
@@ -609,9 +660,12 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             __syncthreads();
             for (int j = 0; j < nbat; ++j) {
             int b = bb[0];
+            bool skipj = skip[0], quietj = quiet[0];
 #pragma unroll
             for (int u = 1; u < kBatch; ++u)
-                if (j == u) b = bb[u];
+                if (j == u) { b = bb[u]; skipj = skip[u]; quietj = quiet[u]; }
+            if (skipj) continue;
+            if (!quietj && lane == 0) a.w.bchg[b] = t;
             if (ntask + 4 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
                 run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
@@ -1081,6 +1135,8 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
     long np = 0;
     int nq = 0, ambc = 0;
     long long delta = 0;
+    // this wave's items k = wv + i nw (static: the wave's interfacial-cell
+    // segment holds at most ceil(nb / nw) bricks), resolved one per lane
     const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
     for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
         int bl = -1;
