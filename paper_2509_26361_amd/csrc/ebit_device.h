@@ -294,9 +294,10 @@ struct PlaneTask {
                     pt(o, side_b(pk, t), Bx, By);
                     const bool sa = x0 <= Ax, sb = x0 <= Bx;
                     if (sa != sb) {
+                        // from the endpoint left of the line to the one right of it
+                        const double Lx = sa ? Bx : Ax, Ly = sa ? By : Ay, Rx = sa ? Ax : Bx, Ry = sa ? Ay : By;
                         ok[2 * o + t] = true;
-                        key[2 * o + t] = sa ? line_cross<T>((T)x0, (T)Bx, (T)By, (T)Ax, (T)Ay)
-                                            : line_cross<T>((T)x0, (T)Ax, (T)Ay, (T)Bx, (T)By);
+                        key[2 * o + t] = line_cross<T>((T)x0, (T)Lx, (T)Ly, (T)Rx, (T)Ry);
                         ++m;
                     }
                 }
@@ -312,16 +313,23 @@ struct PlaneTask {
             fallback += 1;
             return T(0.5);
         }
-        if (m > 1) multi += 1;
         int pick = 0;
+        if (m == 1) {
 #pragma unroll
-        for (int c0 = 0; c0 < 6; ++c0) {
-            if (!ok[c0]) continue;
-            int rank = 0;
+            for (int c0 = 5; c0 >= 0; --c0)
+                if (ok[c0]) pick = c0;
+        } else {
+            multi += 1;
+            // the median crossing by height (ties: enumeration order)
 #pragma unroll
-            for (int c1 = 0; c1 < 6; ++c1)
-                if (ok[c1] && (key[c1] < key[c0] || (key[c1] == key[c0] && c1 < c0))) ++rank;
-            if (rank == (m >> 1)) pick = c0;
+            for (int c0 = 0; c0 < 6; ++c0) {
+                if (!ok[c0]) continue;
+                int rank = 0;
+#pragma unroll
+                for (int c1 = 0; c1 < 6; ++c1)
+                    if (ok[c1] && (key[c1] < key[c0] || (key[c1] == key[c0] && c1 < c0))) ++rank;
+                if (rank == (m >> 1)) pick = c0;
+            }
         }
         // the chosen segment, selected with compile-time indices (no scratch)
         const int fo = o0 + (pick >> 1);
