@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--surr-rows", type=int, default=2_000_000, help="training rows (unambiguous cells)")
     p.add_argument("--surr-steps", type=int, default=20000, help="Adam steps")
     p.add_argument("--surr-batch", type=int, default=8192)
-    p.add_argument("--timing-every", type=int, default=8,
+    p.add_argument("--timing-every", type=int, default=32,
                    help="bracket every k-th launch of each kernel with HIP events (the roofline's duration)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB (float32 read + write), for scaling "
