@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=16)
+    p.add_argument("--workload", default="deformation", choices=["deformation", "mixed"],
+                   help="deformation: the 256^3 deformation test (the default line); mixed: 512^3, 4096 random "
+                        "spheres in a random divergence-free field, 100 steps")
     p.add_argument("--n", type=int, default=256)
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -75,8 +78,10 @@ def kernel_source_hash():
 def stored_traffic(kernel, n, precision):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
-    none for this workload or the kernels changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_deformation_{n}_{precision}.md")
+    none for this workload or the kernels changed since it was taken.  `n` is
+    the grid size of the deformation workload or a workload name."""
+    name = n if isinstance(n, str) else f"deformation_{n}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}_{precision}.md")
     if not os.path.exists(path):
         return None
     sha = kernel_source_hash()
@@ -144,6 +149,8 @@ def main():
         return
     from paper_2509_26361_amd import ebit as E
     from paper_2509_26361_amd import inputs as I
+    if a.workload == "mixed":
+        return run_mixed(a, E, I, torch)
 
     n = a.n
     dt = 0.5 / n
@@ -230,10 +237,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
+def train_surrogate(E, I, torch, a):
     """Learned Front2VOF: training rows from the method's own FP64 runs of
-    seeded ellipsoids at 128^3, training on the GPU (bf16 matrix cores), then
-    the FP32 form with the surrogate on the same workload, against FP64."""
+    seeded ellipsoids at 128^3, training on the GPU (bf16 matrix cores).
+    Returns the parameters and a report."""
     from paper_2509_26361_amd import surrogate as SG
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -286,6 +293,23 @@ def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
     fwd_s = s_ev.elapsed_time(e_ev) * 1e-3 / reps
     del Xt, ct, tr
     torch.cuda.empty_cache()
+    info = {
+        "rows": m, "holdout_rows": nval, "dataset_s": t_data, "train_s": t_train,
+        "steps": a.surr_steps, "batch": a.surr_batch,
+        "holdout_mae": mae, "holdout_max_err": mx, "holdout_bias": bias, "untrained_mae": mae0,
+        "gradient_us": grad_s * 1e6,
+        "gradient_tflops": MLP_GRAD_FLOP * a.surr_batch / grad_s / 1e12,
+        "forward_rows_per_s": nval / fwd_s,
+        "forward_tflops": MLP_FWD_FLOP * nval / fwd_s / 1e12,
+        "bf16_mfma_peak_tflops": 2500.0,
+    }
+    return theta, info
+
+
+def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
+    """The FP32 form with the trained surrogate on the benchmark workload,
+    against the FP64 run."""
+    theta, info = train_surrogate(E, I, torch, a)
     q = run_case(E, I, torch, n, "fp32", W, K, events=True, theta=theta, every=a.timing_every)
     V = q["st1"]["volume"] + q["st1"]["volume_comp"]
     es = float((q["C"] - q["C0"]).abs().sum() / q["C0"].sum())
@@ -299,17 +323,113 @@ def surrogate_form(E, I, torch, n, W, K, a, C64, V64, e_shape64):
         "e_shape_ratio_over_fp64": (es / e_shape64) if (q["ended_at_T"] and e_shape64) else None,
         "ambiguous_cells_end": q["st1"]["n_ambiguous"],
         "interfacial_cells_end": q["st1"]["n_interfacial"],
-        "training": {
-            "rows": m, "holdout_rows": nval, "dataset_s": t_data, "train_s": t_train,
-            "steps": a.surr_steps, "batch": a.surr_batch,
-            "holdout_mae": mae, "holdout_max_err": mx, "holdout_bias": bias, "untrained_mae": mae0,
-            "gradient_us": grad_s * 1e6,
-            "gradient_tflops": MLP_GRAD_FLOP * a.surr_batch / grad_s / 1e12,
-            "forward_rows_per_s": nval / fwd_s,
-            "forward_tflops": MLP_FWD_FLOP * nval / fwd_s / 1e12,
-            "bf16_mfma_peak_tflops": 2500.0,
-        },
+        "training": info,
     }
+
+
+def mixed_case(E, I, torch, n, precision, W, K, phi, pf, U64, every, theta=None):
+    """W untimed and K timed steps of the mixed workload (steady field, g = 1)."""
+    dev = torch.device("cuda:0")
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    Ud = [u.to(dtype) for u in U64]
+    dt = 0.5 / n
+    e = E.Ebit(n, precision, dev)
+    e.init(phi, pf)
+    if theta is not None:
+        e.set_surrogate(theta)
+    C = torch.zeros((n, n, n), dtype=dtype, device=dev)
+    e.front2vof(C)
+    e.advance(Ud, [1.0] * W, dt, C)
+    st0 = e.stats(C)
+    e.set_option(E.EBIT_OPT_TIMING, every)
+    e.timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.advance(Ud, [1.0] * K, dt, C)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = e.timing()
+    st1 = e.stats(C)
+    n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
+    res = {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "C": C,
+           "kt": {"sweep": (tm["sweeps"], tm["sweep_ms"] * 1e-3), "f2v": (tm["f2v"], tm["f2v_ms"] * 1e-3)}}
+    del e, Ud
+    return res
+
+
+def run_mixed(a, E, I, torch):
+    """The large mixed run: 512^3, 4096 seeded non-overlapping spheres with
+    radii U(3, 12) cells (surfaces at least 2 cells apart), a seeded
+    divergence-free random Fourier field (8 modes per component, max |u| = 1),
+    CFL 0.5, FP64; the FP32 form and the FP32 form with the surrogate are
+    compared with it."""
+    n, dev = 512, torch.device("cuda:0")
+    K = a.steps if a.steps is not None else 100
+    W = a.warmup
+    log = lambda msg: print(f"[bench] mixed: {msg}", file=sys.stderr, flush=True)
+    log("placing spheres")
+    cs, rs = I.random_nonoverlapping_spheres(4096, 3.0, 12.0, n, gap_cells=2.0, seed=0)
+    log(f"{len(rs)} spheres; sampling phi")
+    sh = I.spheres_shape(n, cs, rs, with_s=False)
+    phi = torch.from_numpy(sh.phi_nodes).to(dev)
+    pf = [torch.from_numpy(f).to(dev) for f in sh.phi_faces]
+    del sh
+    U = I.fourier_velocity_device(n, seed=1, modes=8, device=dev)
+    log("fp64 run")
+    r = mixed_case(E, I, torch, n, "fp64", W, K, phi, pf, U, a.timing_every)
+    kt = r["kt"]
+    tot = {k: v[1] for k, v in kt.items()}
+    dom = max(tot, key=tot.get)
+    avg_dur = tot[dom] / max(1, kt[dom][0])
+    units = r["n_start"] / K
+    achieved = BYTES["fp64"][dom] * units / avg_dur / 1e9
+    V64 = r["st1"]["volume"] + r["st1"]["volume_comp"]
+    out = {
+        "metric": "interfacial cell-updates/s (advect+Front2VOF), 512^3 mixed run; vol err vs FP64",
+        "value": r["n_start"] / r["wall"],
+        "unit": "interfacial cell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": r["wall"] / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"mixed_512: {len(rs)} random spheres r U(3,12) cells, gap 2 cells, random "
+                               f"divergence-free Fourier field (8 modes/component, max|u| = 1), CFL 0.5, "
+                               f"steps {W}..{W + K}", "n": n, "precision": "fp64", "sweeps_per_step": 3},
+        "roofline": {"kernel": "k_sweep (ebit_advect_sweep)" if dom == "sweep" else "k_f2v (ebit_front2vof)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic("k_sweep" if dom == "sweep" else "k_f2v", "mixed_512", "fp64"),
+                     "bytes_per_unit": BYTES["fp64"][dom], "units_per_launch": units,
+                     "avg_launch_us": avg_dur * 1e6, "timed_launches": kt[dom][0]},
+        "launch_us": {k: (kt[k][1] / kt[k][0] * 1e6 if kt[k][0] else None) for k in kt},
+        "interfacial_cells": {"start": r["st0"]["n_interfacial"], "end": r["st1"]["n_interfacial"], "mean": units},
+        "volume": {"start": r["st0"]["volume"] + r["st0"]["volume_comp"], "end": V64},
+        "counters": {k: r["st1"][k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged")},
+    }
+    C64 = r["C"]
+    del r
+    torch.cuda.empty_cache()
+    forms = []
+    if not a.no_fp32:
+        forms.append(("fp32_form", None))
+    if not a.no_surrogate:
+        theta, info = train_surrogate(E, I, torch, a)
+        forms.append(("fp32_surrogate_form", (theta, info)))
+    for name, surr in forms:
+        log(name)
+        q = mixed_case(E, I, torch, n, "fp32", W, K, phi, pf, U, a.timing_every,
+                       theta=surr[0] if surr else None)
+        V = q["st1"]["volume"] + q["st1"]["volume_comp"]
+        out[name] = {"value": q["n_start"] / q["wall"], "ms_per_step": q["wall"] / K * 1e3,
+                     "launch_us": {k: (q["kt"][k][1] / q["kt"][k][0] * 1e6 if q["kt"][k][0] else None)
+                                   for k in q["kt"]},
+                     "volume_rel_err_vs_fp64": abs(V - V64) / V64,
+                     "max_abs_C_diff_vs_fp64": float((q["C"].double() - C64).abs().max())}
+        if surr:
+            out[name]["ambiguous_cells_end"] = q["st1"]["n_ambiguous"]
+            out[name]["training"] = surr[1]
+        del q
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(n, budget_s):

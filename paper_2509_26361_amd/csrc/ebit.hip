@@ -85,14 +85,16 @@ struct Geo {
 int waves_for(int n)
 {
     const long nb = (long)(n / 4) * (n / 4) * (n / 4);
-    return (int)(nb < 64 ? 64 : (nb > kMaxWaves ? kMaxWaves : nb));
+    const long w = nb < 64 ? 64 : (nb > kMaxWaves ? kMaxWaves : nb);
+    return (int)(w & ~7L);      // a whole number of waves per XCD
 }
 
+// items per wave are at most ceil(nb / nw) + 2 under item_of()
 long segcap_for(int n)
 {
     const long nb = (long)(n / 4) * (n / 4) * (n / 4);
     const long nw = waves_for(n);
-    return ((nb + nw - 1) / nw) * 64;
+    return ((nb + nw - 1) / nw + 2) * 64;
 }
 
 // device work space carved out of the caller's scratch buffer
@@ -233,6 +235,20 @@ __device__ __forceinline__ void claim_two(const int *srcA, int na, const int *sr
             pB += (uint32_t)__popcll(balB[u]);
         }
     }
+}
+
+// The i-th item of wave w (of nw, a multiple of 8).  Items go in chunks of
+// kXcdChunk consecutive list entries -- bricks appended together, hence
+// neighbours -- and chunk c to the waves of XCD c mod 8 (workgroup ids are
+// dealt to the eight XCDs round robin), which take the XCD's items round
+// robin: neighbouring bricks are processed near each other in time under one
+// L2, which then serves the halos they share.  Increasing in i.
+constexpr uint32_t kXcdChunk = 16;
+__device__ __forceinline__ uint32_t item_of(uint32_t w, uint32_t i, uint32_t nw)
+{
+    const uint32_t x = w & 7u, nj = nw >> 3;
+    const uint32_t idx = (w >> 3) + i * nj;
+    return ((idx / kXcdChunk) * 8u + x) * kXcdChunk + idx % kXcdChunk;
 }
 
 // Items of a grid: the concatenation of up to two lists of kSub sub-lists
@@ -510,16 +526,14 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
         nm = 0;
         nc = 0;
     };
-    // this wave's items k = wv + i nw, resolved one per lane (a static
+    // this wave's items item_of(wv, i), resolved one per lane (a static
     // schedule: a shared counter handing out items cost more than the
     // imbalance it removes)
-    const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
-    for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
+    for (uint32_t i0 = 0; item_of((uint32_t)wv, i0, (uint32_t)nw) < it.total; i0 += 64) {
         int bl = -1;
         {
-            const uint32_t i = i0 + (uint32_t)lane;
-            const uint32_t k = (uint32_t)wv + i * (uint32_t)nw;
-            const bool have = i < mine;
+            const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
+            const bool have = k < it.total;
             int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
             if (!have || bb < 0 || bb >= nb) bb = -1;
             if (bb >= 0 && !a.full && k >= it.nfirst && cm_cur[bb] == t) bb = -1;   // also in this sweep's own list
@@ -1135,15 +1149,13 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
     long np = 0;
     int nq = 0, ambc = 0;
     long long delta = 0;
-    // this wave's items k = wv + i nw (static: the wave's interfacial-cell
-    // segment holds at most ceil(nb / nw) bricks), resolved one per lane
-    const uint32_t mine = it.total > (uint32_t)wv ? (it.total - (uint32_t)wv + (uint32_t)nw - 1) / (uint32_t)nw : 0;
-    for (uint32_t i0 = 0; i0 < mine; i0 += 64) {
+    // this wave's items item_of(wv, i) (static: the wave's interfacial-cell
+    // segment holds the at most ceil(nb / nw) + 2 bricks), resolved one per lane
+    for (uint32_t i0 = 0; item_of((uint32_t)wv, i0, (uint32_t)nw) < it.total; i0 += 64) {
         int bl = -1;
         {
-            const uint32_t i = i0 + (uint32_t)lane;
-            const uint32_t k = (uint32_t)wv + i * (uint32_t)nw;
-            const bool have = i < mine;
+            const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
+            const bool have = k < it.total;
             int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
             if (!have || bb < 0 || bb >= nb) bb = -1;
             bl = bb;

@@ -40,6 +40,7 @@ __all__ = [
     "deformation_velocity",
     "deformation_time_factor",
     "fourier_velocity",
+    "fourier_velocity_device",
     "random_nonoverlapping_spheres",
     "WORKLOADS",
 ]
@@ -121,7 +122,7 @@ def sphere_shape(n, centre=(0.35, 0.35, 0.35), R=0.15) -> Shape:
     return Shape(n, phi, faces, _sphere_edge_roots(n, centre, R))
 
 
-def spheres_shape(n, centres, radii) -> Shape:
+def spheres_shape(n, centres, radii, with_s=True) -> Shape:
     """Union of disjoint spheres: at each sample point the largest
     ``R^2 - |x-c|^2`` over the spheres, positive exactly inside the union.
     Each sphere is rasterised only over its bounding box (plus a margin) so
@@ -145,7 +146,7 @@ def spheres_shape(n, centres, radii) -> Shape:
             val = R * R - (comps[2][:, None, None] + comps[1][None, :, None] + comps[0][None, None, :])
             tgt = phi if which == 0 else faces[which - 1]
             tgt[sel] = np.maximum(tgt[sel], val)
-    s = [np.full((n, n, n), 0.5) for _ in range(3)]
+    s = [np.full((n, n, n), 0.5) for _ in range(3)] if with_s else None
     return Shape(n, phi, faces, s)
 
 
@@ -236,16 +237,11 @@ def deformation_time_factor(t, T=3.0):
     return math.cos(math.pi * t / T)
 
 
-def fourier_velocity(n, seed=1, modes=8):
-    """Seeded divergence-free periodic field u = curl A.
-
-    A has ``modes`` random Fourier modes per component with integer wave
-    vectors in {-8..8}^3 \\ 0, amplitudes N(0,1)/|k| and uniform phases; the
-    curl is taken analytically at the nodes and the field is scaled so that
-    the largest nodal speed is 1."""
+def _fourier_modes(seed, modes):
+    """The random draws of fourier_velocity: per component of A, `modes`
+    (wave vector, amplitude, phase) triples."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    x = np.arange(n) / n
-    u = [np.zeros((n, n, n)) for _ in range(3)]
+    out = []
     for comp in range(3):
         for _ in range(modes):
             while True:
@@ -254,28 +250,56 @@ def fourier_velocity(n, seed=1, modes=8):
                     break
             amp = rng.normal() / np.linalg.norm(k)
             ph = rng.uniform(0.0, 2.0 * np.pi)
-            # A_comp = amp * cos(2 pi k.x + ph);  dA/dx_b = -amp 2 pi k_b sin(...)
-            # separable evaluation of sin(2 pi k.x + ph) via 1D phase tables
-            ex = [np.exp(1j * 2 * np.pi * k[a] * x) for a in range(3)]
-            arg = (ex[2][:, None, None] * ex[1][None, :, None] * ex[0][None, None, :]) * np.exp(1j * ph)
-            sn = arg.imag
-            for b in range(3):
-                d = -amp * 2 * np.pi * k[b] * sn          # dA_comp / dx_b
-                # curl: u_x = dA_z/dy - dA_y/dz, u_y = dA_x/dz - dA_z/dx, u_z = dA_y/dx - dA_x/dy
-                if comp == 2 and b == 1:
-                    u[0] += d
-                if comp == 1 and b == 2:
-                    u[0] -= d
-                if comp == 0 and b == 2:
-                    u[1] += d
-                if comp == 2 and b == 0:
-                    u[1] -= d
-                if comp == 1 and b == 0:
-                    u[2] += d
-                if comp == 0 and b == 1:
-                    u[2] -= d
+            out.append((comp, k, amp, ph))
+    return out
+
+
+# curl: u_x = dA_z/dy - dA_y/dz, u_y = dA_x/dz - dA_z/dx, u_z = dA_y/dx - dA_x/dy;
+# (comp, b) -> (velocity component, sign) for dA_comp / dx_b
+_CURL = {(2, 1): (0, 1.0), (1, 2): (0, -1.0), (0, 2): (1, 1.0), (2, 0): (1, -1.0), (1, 0): (2, 1.0), (0, 1): (2, -1.0)}
+
+
+def fourier_velocity(n, seed=1, modes=8):
+    """Seeded divergence-free periodic field u = curl A.
+
+    A has ``modes`` random Fourier modes per component with integer wave
+    vectors in {-8..8}^3 \\ 0, amplitudes N(0,1)/|k| and uniform phases; the
+    curl is taken analytically at the nodes and the field is scaled so that
+    the largest nodal speed is 1."""
+    x = np.arange(n) / n
+    u = [np.zeros((n, n, n)) for _ in range(3)]
+    for comp, k, amp, ph in _fourier_modes(seed, modes):
+        # A_comp = amp * cos(2 pi k.x + ph);  dA/dx_b = -amp 2 pi k_b sin(...), the
+        # sine evaluated separably from 1D phase tables
+        ex = [np.exp(1j * 2 * np.pi * k[a] * x) for a in range(3)]
+        arg = (ex[2][:, None, None] * ex[1][None, :, None] * ex[0][None, None, :]) * np.exp(1j * ph)
+        sn = arg.imag
+        for b in range(3):
+            if (comp, b) in _CURL:
+                c, sg = _CURL[(comp, b)]
+                u[c] += sg * (-amp * 2 * np.pi * k[b] * sn)
     mag = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2).max()
     return [np.ascontiguousarray(c / mag) for c in u]
+
+
+def fourier_velocity_device(n, seed=1, modes=8, device="cuda", dtype=None):
+    """The field of fourier_velocity (same draws), evaluated with torch on a
+    device in float64 -- for grids where the host version is slow."""
+    import torch
+    dt = torch.float64
+    x = torch.arange(n, dtype=dt, device=device) / n
+    u = [torch.zeros((n, n, n), dtype=dt, device=device) for _ in range(3)]
+    for comp, k, amp, ph in _fourier_modes(seed, modes):
+        th = [2 * math.pi * float(k[a]) * x for a in range(3)]
+        ang = th[2][:, None, None] + th[1][None, :, None] + th[0][None, None, :] + ph
+        sn = torch.sin(ang)
+        for b in range(3):
+            if (comp, b) in _CURL:
+                c, sg = _CURL[(comp, b)]
+                u[c] += sg * (-amp * 2 * math.pi * float(k[b])) * sn
+        del ang, sn
+    mag = torch.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2).max()
+    return [(c / mag).to(dtype or dt).contiguous() for c in u]
 
 
 def random_nonoverlapping_spheres(count, rmin_cells, rmax_cells, n, gap_cells=2.0, seed=0,
