@@ -403,11 +403,12 @@ struct SweepArgs {
 // indexed iD + kAD (i1 + kAA i2), (iD, i1, i2) = offsets (+1, 0, 0) along (D, A1, A2).
 constexpr int kAD = 6, kAA = 5, kATile = kAD * kAA * kAA;
 
-// The queued tasks of a sweep wave, one per lane: the circle-fit placement of
-// a new unaligned marker (type bit 1 clear) or the colour of a face whose
-// corners differ (bit 1 set) in the plane (D, A1) (bit 0 clear) or (D, A2);
-// bit 2 is the node's new colour.  Face colours are gathered per node in the
-// slot table and the node's flags byte is written once.
+// The queued tasks of a sweep wave, one per lane: a node whose face in the
+// plane (D, A1) (type bit 0 clear) or (D, A2) has differing corners -- that
+// face's colour, and with type bit 1 the circle-fit placement of the node's
+// new marker on the edge across (whose end colours differ, so the face's
+// corners do too); bit 2 is the node's new colour.  Face colours are gathered
+// per node in the slot table and the node's flags byte is written once.
 template <typename T, int D>
 __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t *tq, const uint8_t *tt,
                                           const uint8_t *ts, int ntask, const uint32_t *sq, uint32_t *sb,
@@ -424,7 +425,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
             const long q = tq[i];
             const int ty = tt[i];
             const bool second = ty & 1;             // plane (D, A2)
-            const int face = (ty >> 1) & 1, c00 = (ty >> 2) & 1;
+            const int unal = (ty >> 1) & 1, c00 = (ty >> 2) & 1;
             const int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / nn)};
             PlaneTask<T, D> p;
             p.fl = a.fl;
@@ -442,9 +443,10 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
             p.vb = second ? 4 + A2 : 4 + A1;
             p.fb = second ? 1 + A1 : 1 + A2;
             p.fetch_flags();
-            const T v = p.run(face, c00, fbt, multit);
-            if (!face) (second ? a.so[A2] : a.so[A1])[q] = v;
-            else if (v != T(0)) atomicOr(&sb[ts[i]], 1u << p.fb);
+            T sv = T(0);
+            const int par = p.run(unal, c00, sv, fbt, multit);
+            if (unal) (second ? a.so[A2] : a.so[A1])[q] = sv;
+            if (par) atomicOr(&sb[ts[i]], 1u << p.fb);
         }
     }
     __syncthreads();
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                 if (j == u) { b = bb[u]; skipj = skip[u]; quietj = quiet[u]; }
             if (skipj) continue;
             if (!quietj && lane == 0) a.w.bchg[b] = t;
-            if (ntask + 4 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
+            if (ntask + 2 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
                 run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
                 nslot = 0;
@@ -744,21 +746,25 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             // queue: unaligned markers of both planes, then the face nodes and their faces
             {
                 const unsigned long long lt = (1ull << lane) - 1ull;
-                unsigned long long bal = __ballot(task[0]);
-                if (task[0]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = 0; }
-                ntask += __popcll(bal);
-                bal = __ballot(task[1]);
-                if (task[1]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = 1; }
-                ntask += __popcll(bal);
-                bal = __ballot(fnode);
+                unsigned long long bal = __ballot(fnode);
                 const int slot = nslot + __popcll(bal & lt);
                 if (fnode) { sq[slot] = (uint32_t)qs; sb[slot] = out; }
                 nslot += __popcll(bal);
                 bal = __ballot(task[2]);
-                if (task[2]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = (uint8_t)(2 | (c00 << 2)); ts[i] = (uint8_t)slot; }
+                if (task[2]) {
+                    const int i = ntask + __popcll(bal & lt);
+                    tq[i] = (uint32_t)qs;
+                    tt[i] = (uint8_t)(0 | ((int)task[0] << 1) | (c00 << 2));
+                    ts[i] = (uint8_t)slot;
+                }
                 ntask += __popcll(bal);
                 bal = __ballot(task[3]);
-                if (task[3]) { int i = ntask + __popcll(bal & lt); tq[i] = (uint32_t)qs; tt[i] = (uint8_t)(3 | (c00 << 2)); ts[i] = (uint8_t)slot; }
+                if (task[3]) {
+                    const int i = ntask + __popcll(bal & lt);
+                    tq[i] = (uint32_t)qs;
+                    tt[i] = (uint8_t)(1 | ((int)task[1] << 1) | (c00 << 2));
+                    ts[i] = (uint8_t)slot;
+                }
                 ntask += __popcll(bal);
             }
             // lists: the next sweep takes the bricks next to a brick holding

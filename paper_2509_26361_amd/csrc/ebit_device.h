@@ -216,102 +216,107 @@ struct PlaneTask {
         else { Xb = (double)xb + (double)delb; Yb = (double)yb + (double)s_b; }
     }
 
-    // The task.  face = 0: the new marker on V(0,0) (the caller knows the new
-    // end colours differ): crossings of X = 0 by the advected old segments of
-    // faces -2..0 of the row; the median one (by height) is refined by the
-    // circle fit (sec. 2.1).  face = 1: colour at the centre of Q(0,0) relative
-    // to the advected polyline: start from the node's new colour c00, flip for
-    // aligned markers landing in [0, 1/2) on the bottom line and for advected
-    // segments of faces -1..1 crossing X = 1/2 below Y = 1/2.  Returns the
-    // fraction (face = 0) or the colour (face = 1).
-    __device__ __forceinline__ T run(int face, int c00, int &fallback, int &multi) const
+    // The task of one node in this plane (sec. 2.1, 2.3).  Always: the colour
+    // at the centre of Q(0,0) relative to the advected polyline -- start from
+    // the node's new colour c00, flip for aligned markers landing in [0, 1/2)
+    // on the bottom line and for advected segments of faces -1..1 crossing
+    // X = 1/2 below Y = 1/2 (returned).  With `unal` (the new end colours of
+    // V(0,0) differ): the new marker on V(0,0) -- crossings of X = 0 by the
+    // advected old segments of faces -2..0 of the row, the median one (by
+    // height) refined by the circle fit (*sval).  Faces -2..1 of the row share
+    // one round of loads, issued before any arithmetic (a missing marker reads
+    // a valid entry and is masked).
+    __device__ __forceinline__ int run(int unal, int c00, T &sval, int &fallback, int &multi) const
     {
-        const int o0 = face ? -1 : -2;
-        const double x0 = face ? 0.5 : 0.0;
-        // markers of the candidate faces Q(o0+o, 0), o = 0..2 (X, Y relative to
-        // the node): the velocities at nodes (o0+k, r), k = 0..3, r = 0, 1 serve
-        // both edge families; every load is issued before any arithmetic (a
-        // missing marker reads a valid entry and is masked)
-        uint32_t qn[4][2];
+        // velocities at nodes (k - 2, r), k = 0..4, r = 0, 1; fractions of H(f - 2, r),
+        // f = 0..3, and of V(k - 2, 0)
+        uint32_t qn[5][2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) qn[k][r] = (face ? xo[k + 2] : xo[k + 1]) + yo[r + 1];
-        T Un[4][2], sh_[3][2], sv_[4];
+            for (int r = 0; r < 2; ++r) qn[k][r] = xo[k + 1] + yo[r + 1];
+        T Un[5][2], sh_[4][2], sv_[5];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 5; ++k)
 #pragma unroll
             for (int r = 0; r < 2; ++r) Un[k][r] = U[qn[k][r]];
 #pragma unroll
-        for (int o = 0; o < 3; ++o)
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) sh_[o][r] = sD[qn[o][r]];
+            for (int r = 0; r < 2; ++r) sh_[f][r] = sD[qn[f][r]];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sv_[k] = sA[qn[k][0]];
-        double Hx[3][2], Vx[4], Vy[4];
+        for (int k = 0; k < 5; ++k) sv_[k] = sA[qn[k][0]];
+        // advected markers (X, Y relative to the node)
+        double Hx[4][2], Vx[5], Vy[5];
 #pragma unroll
-        for (int o = 0; o < 3; ++o)
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const T sx = sh_[o][r], u0 = Un[o][r];
-                const T del = c * (u0 + sx * (Un[o + 1][r] - u0));
-                Hx[o][r] = hhas(o0 + o, r) ? (double)(o0 + o) + ((double)sx + (double)del) : 0.0;
+                const T sx = sh_[f][r], u0 = Un[f][r];
+                const T del = c * (u0 + sx * (Un[f + 1][r] - u0));
+                Hx[f][r] = hhas(f - 2, r) ? (double)(f - 2) + ((double)sx + (double)del) : 0.0;
             }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 5; ++k) {
             const T sy = sv_[k], u0 = Un[k][0];
             const T del = c * (u0 + sy * (Un[k][1] - u0));
-            const bool v = vhas(o0 + k, 0);
-            Vx[k] = v ? (double)(o0 + k) + (double)del : 0.0;
+            const bool v = vhas(k - 2, 0);
+            Vx[k] = v ? (double)(k - 2) + (double)del : 0.0;
             Vy[k] = v ? 0.0 + (double)sy : 0.0;
         }
-        auto pt = [&](int o, int side, double &X, double &Y) {
-            X = side == 0 ? Hx[o][0] : (side == 2 ? Hx[o][1] : (side == 3 ? Vx[o] : Vx[o + 1]));
-            Y = side == 0 ? 0.0 : (side == 2 ? 1.0 : (side == 3 ? Vy[o] : Vy[o + 1]));
+        // side of face f - 2 (see point())
+        auto pt = [&](int f, int side, double &X, double &Y) {
+            X = side == 0 ? Hx[f][0] : (side == 2 ? Hx[f][1] : (side == 3 ? Vx[f] : Vx[f + 1]));
+            Y = side == 0 ? 0.0 : (side == 2 ? 1.0 : (side == 3 ? Vy[f] : Vy[f + 1]));
         };
-        int par = c00;
-        if (face) {
+        int pk[4];
 #pragma unroll
-            for (int o = 0; o < 3; ++o) {
-                if (!hhas(o0 + o, 0)) continue;
-                const double X = Hx[o][0];
-                if (0.0 <= X && X < 0.5) par ^= 1;
-            }
+        for (int f = 0; f < 4; ++f) pk[f] = pairs(f - 2, 0);
+        // crossing of segment t of face f with the line X = x0 (from the endpoint left of
+        // the line to the one right of it); false if the segment does not cross it
+        auto cross = [&](int f, int t, double x0, T &key) -> bool {
+            if (t >= nseg(pk[f])) return false;
+            double Ax, Ay, Bx, By;
+            pt(f, side_a(pk[f], t), Ax, Ay);
+            pt(f, side_b(pk[f], t), Bx, By);
+            const bool sa = x0 <= Ax, sb = x0 <= Bx;
+            if (sa == sb) return false;
+            const double Lx = sa ? Bx : Ax, Ly = sa ? By : Ay, Rx = sa ? Ax : Bx, Ry = sa ? Ay : By;
+            key = line_cross<T>((T)x0, (T)Lx, (T)Ly, (T)Rx, (T)Ry);
+            return true;
+        };
+        // face-centre colour (faces -1..1)
+        int par = c00;
+#pragma unroll
+        for (int f = 1; f < 4; ++f) {
+            if (!hhas(f - 2, 0)) continue;
+            const double X = Hx[f][0];
+            if (0.0 <= X && X < 0.5) par ^= 1;
         }
+#pragma unroll
+        for (int f = 1; f < 4; ++f)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                T y;
+                if (cross(f, t, 0.5, y) && y < T(0.5)) par ^= 1;
+            }
+        if (!unal) return par;
+        // new marker on V(0,0) (faces -2..0)
         T key[6];
         bool ok[6];
         int m = 0;
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-            const int pk = pairs(o0 + o, 0);
+        for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                ok[2 * o + t] = false;
-                key[2 * o + t] = T(0);
-                if (t < nseg(pk)) {
-                    double Ax, Ay, Bx, By;
-                    pt(o, side_a(pk, t), Ax, Ay);
-                    pt(o, side_b(pk, t), Bx, By);
-                    const bool sa = x0 <= Ax, sb = x0 <= Bx;
-                    if (sa != sb) {
-                        // from the endpoint left of the line to the one right of it
-                        const double Lx = sa ? Bx : Ax, Ly = sa ? By : Ay, Rx = sa ? Ax : Bx, Ry = sa ? Ay : By;
-                        ok[2 * o + t] = true;
-                        key[2 * o + t] = line_cross<T>((T)x0, (T)Lx, (T)Ly, (T)Rx, (T)Ry);
-                        ++m;
-                    }
-                }
+                key[2 * f + t] = T(0);
+                ok[2 * f + t] = cross(f, t, 0.0, key[2 * f + t]);
+                m += ok[2 * f + t] ? 1 : 0;
             }
-        }
-        if (face) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                if (ok[k] && key[k] < T(0.5)) par ^= 1;
-            return (T)par;
-        }
         if ((m & 1) == 0) {          // no odd crossing set: keep the edge valid
             fallback += 1;
-            return T(0.5);
+            sval = T(0.5);
+            return par;
         }
         int pick = 0;
         if (m == 1) {
@@ -332,16 +337,15 @@ struct PlaneTask {
             }
         }
         // the chosen segment, selected with compile-time indices (no scratch)
-        const int fo = o0 + (pick >> 1);
+        const int fo = (pick >> 1) - 2;
         int sa_ = 0, sb_ = 0;
         double Ax = 0.0, Ay = 0.0, Bx = 0.0, By = 0.0;
         T kp = T(0);
 #pragma unroll
         for (int c0 = 0; c0 < 6; ++c0) {
             if (c0 != pick) continue;
-            const int pk = pairs(o0 + (c0 >> 1), 0);
-            sa_ = side_a(pk, c0 & 1);
-            sb_ = side_b(pk, c0 & 1);
+            sa_ = side_a(pk[c0 >> 1], c0 & 1);
+            sb_ = side_b(pk[c0 >> 1], c0 & 1);
             pt(c0 >> 1, sa_, Ax, Ay);
             pt(c0 >> 1, sb_, Bx, By);
             kp = key[c0];
@@ -355,7 +359,8 @@ struct PlaneTask {
         neighbour(fo, 0, s2, n1i, n1j, n1s);
         neighbour(fo, 0, s3, n4i, n4j, n4s);
         two_points(n1i, n1j, n1s, n4i, n4j, n4s, P1x, P1y, P4x, P4y);
-        return fit_height<T>((T)P1x, (T)P1y, (T)P2x, (T)P2y, (T)P3x, (T)P3y, (T)P4x, (T)P4y, kp);
+        sval = fit_height<T>((T)P1x, (T)P1y, (T)P2x, (T)P2y, (T)P3x, (T)P3y, (T)P4x, (T)P4y, kp);
+        return par;
     }
 };
 
