@@ -144,10 +144,20 @@ size_t work_layout(int n, Work *w, char *base)
     return off;
 }
 
-__device__ __forceinline__ int brick_shift(int b, int nb1, int dx, int dy, int dz)
+// Bricks in lists are packed coordinates bx | by << 10 | bz << 20 (at most
+// 256 bricks per axis); per-brick arrays are indexed by bx + nb1 (by + nb1 bz).
+__device__ __forceinline__ uint32_t bpack(int bx, int by, int bz)
 {
-    int bx = b % nb1, by = (b / nb1) % nb1, bz = b / (nb1 * nb1);
-    return wrp(bx + dx, nb1) + nb1 * (wrp(by + dy, nb1) + nb1 * wrp(bz + dz, nb1));
+    return (uint32_t)bx | ((uint32_t)by << 10) | ((uint32_t)bz << 20);
+}
+__device__ __forceinline__ int bx_of(uint32_t p) { return (int)(p & 1023u); }
+__device__ __forceinline__ int by_of(uint32_t p) { return (int)((p >> 10) & 1023u); }
+__device__ __forceinline__ int bz_of(uint32_t p) { return (int)(p >> 20); }
+__device__ __forceinline__ int blin(uint32_t p, int nb1) { return bx_of(p) + nb1 * (by_of(p) + nb1 * bz_of(p)); }
+__device__ __forceinline__ uint32_t bpack_lin(int b, int nb1) { return bpack(b % nb1, (b / nb1) % nb1, b / (nb1 * nb1)); }
+__device__ __forceinline__ uint32_t brick_shift(uint32_t p, int nb1, int dx, int dy, int dz)
+{
+    return bpack(wrp(bx_of(p) + dx, nb1), wrp(by_of(p) + dy, nb1), wrp(bz_of(p) + dz, nb1));
 }
 
 // sum of a per-lane value over the wave (result valid in every lane)
@@ -183,13 +193,13 @@ struct ClaimList {
     uint32_t *num;
 };
 
-__device__ __forceinline__ void claim_two(const int *srcA, int na, const int *srcB, int nbr, int nb1, ClaimList A,
-                                          ClaimList B, int sub, uint32_t cap)
+__device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const uint32_t *srcB, int nbr, int nb1,
+                                          ClaimList A, ClaimList B, int sub, uint32_t cap)
 {
     const int lane = threadIdx.x & 63;
     const int ta = na * 27, total = ta + nbr * 8;
     for (int base = 0; base < total; base += 256) {
-        int nbk[4];
+        uint32_t nbk[4];
         bool take[4], inA[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -198,10 +208,12 @@ __device__ __forceinline__ void claim_two(const int *srcA, int na, const int *sr
             inA[u] = c < ta;
             nbk[u] = 0;
             if (c < ta) {
-                const int b = srcA[c / 27], d = c % 27;
+                const uint32_t b = srcA[c / 27];
+                const int d = c % 27;
                 nbk[u] = brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1);
             } else if (c < total) {
-                const int b = srcB[(c - ta) >> 3], d = (c - ta) & 7;
+                const uint32_t b = srcB[(c - ta) >> 3];
+                const int d = (c - ta) & 7;
                 nbk[u] = brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
             }
         }
@@ -209,7 +221,7 @@ __device__ __forceinline__ void claim_two(const int *srcA, int na, const int *sr
         for (int u = 0; u < 4; ++u) {
             if (base + 64 * u + lane >= total) continue;
             const ClaimList &L = inA[u] ? A : B;
-            take[u] = atomicExch(&L.mark[nbk[u]], L.v) != L.v;
+            take[u] = atomicExch(&L.mark[blin(nbk[u], nb1)], L.v) != L.v;
         }
         unsigned long long balA[4], balB[4];
         int cA = 0, cB = 0;
@@ -229,8 +241,8 @@ __device__ __forceinline__ void claim_two(const int *srcA, int na, const int *sr
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t qa = pA + (uint32_t)__popcll(balA[u] & lt), qb = pB + (uint32_t)__popcll(balB[u] & lt);
-            if (take[u] && inA[u] && qa < cap) A.list[(size_t)sub * cap + qa] = (uint32_t)nbk[u];
-            if (take[u] && !inA[u] && qb < cap) B.list[(size_t)sub * cap + qb] = (uint32_t)nbk[u];
+            if (take[u] && inA[u] && qa < cap) A.list[(size_t)sub * cap + qa] = nbk[u];
+            if (take[u] && !inA[u] && qb < cap) B.list[(size_t)sub * cap + qb] = nbk[u];
             pA += (uint32_t)__popcll(balA[u]);
             pB += (uint32_t)__popcll(balB[u]);
         }
@@ -353,7 +365,8 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         const bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
         if (hasm) {
             const ClaimList A{w.cm[2], 2u, w.blist[2], w.bnum + 2 * kSub};
-            claim_two(&b, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.nb);
+            const uint32_t bp = bpack(bx, by, bz);
+            claim_two(&bp, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.nb);
         }
     }
 }
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
     __shared__ uint32_t tq[kTaskCap];
     __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
-    __shared__ int mbr[kClaimCap], cbr[kClaimCap];
+    __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap];
     const int lane = threadIdx.x;
     const int wv = blockIdx.x, nw = gridDim.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
@@ -536,9 +549,11 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
         {
             const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
             const bool have = k < it.total;
-            int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
-            if (!have || bb < 0 || bb >= nb) bb = -1;
-            if (bb >= 0 && !a.full && k >= it.nfirst && cm_cur[bb] == t) bb = -1;   // also in this sweep's own list
+            // packed brick coordinates (-1: none)
+            int bb = a.full ? (have ? (int)bpack_lin((int)k, nb1) : -1) : it.brick_lane(have ? k : 0);
+            if (!have || bb < 0 || bx_of((uint32_t)bb) >= nb1 || by_of((uint32_t)bb) >= nb1 || bz_of((uint32_t)bb) >= nb1)
+                bb = -1;
+            if (bb >= 0 && !a.full && k >= it.nfirst && cm_cur[blin((uint32_t)bb, nb1)] == t) bb = -1;   // also in this sweep's own list
             bl = bb;
         }
         unsigned long long pend = __ballot(bl >= 0);
@@ -572,7 +587,7 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                 for (int r = 0; r < kR; ++r) fr[j][r] = 0;
                 if (j >= nbat) continue;
                 const int b = bb[j];
-                const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+                const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
                 fown[j] = a.fl[(uint32_t)(org[0] + lu[0]) + __umul24((uint32_t)(org[1] + lu[1]), un) +
                                __umul24((uint32_t)(org[2] + lu[2]), unn)];
 #pragma unroll
@@ -580,7 +595,7 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                     int gpd;
                     fr[j][r] = a.fl[tnode(org, tpk[r], gpd)];
                 }
-                lastchg[j] = a.w.bchg[b];
+                lastchg[j] = a.w.bchg[blin((uint32_t)b, nb1)];
             }
             // A brick whose tile (halo included) holds no marker, and whose
             // faces containing D already carry their nodes' colour, is left
@@ -609,7 +624,7 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
                 sAo[j][0] = sAo[j][1] = UAo[j][0] = UAo[j][1] = Uown[j] = T(0);
                 if (j >= nbat) continue;
                 const int b = bb[j];
-                const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+                const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
 #pragma unroll
                 for (int r = 0; r < kR; ++r) {
                     if ((fr[j][r] >> (4 + D)) & 1) {
@@ -681,14 +696,14 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             for (int u = 1; u < kBatch; ++u)
                 if (j == u) { b = bb[u]; skipj = skip[u]; quietj = quiet[u]; }
             if (skipj) continue;
-            if (!quietj && lane == 0) a.w.bchg[b] = t;
+            if (!quietj && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
             if (ntask + 2 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
                 run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
                 nslot = 0;
             }
             ++nact;
-            const int org[3] = {(b % nb1) * 4, ((b / nb1) % nb1) * 4, (b / (nb1 * nb1)) * 4};
+            const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
             const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
             const uint8_t *tf = tfl[j];
             const double *tx = txd[j];
@@ -774,8 +789,8 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
             const bool hasm = __ballot((out & 0x70) != 0) != 0;
             const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
             if (lane == 0) {
-                if (hasm) mbr[nm] = b;
-                if (hasm || chg) cbr[nc] = b;
+                if (hasm) mbr[nm] = (uint32_t)b;
+                if (hasm || chg) cbr[nc] = (uint32_t)b;
             }
             nm += hasm ? 1 : 0;
             nc += (hasm || chg) ? 1 : 0;
@@ -1162,8 +1177,9 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
         {
             const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
             const bool have = k < it.total;
-            int bb = a.full ? (int)k : it.brick_lane(have ? k : 0);
-            if (!have || bb < 0 || bb >= nb) bb = -1;
+            int bb = a.full ? (have ? (int)bpack_lin((int)k, nb1) : -1) : it.brick_lane(have ? k : 0);
+            if (!have || bb < 0 || bx_of((uint32_t)bb) >= nb1 || by_of((uint32_t)bb) >= nb1 || bz_of((uint32_t)bb) >= nb1)
+                bb = -1;
             bl = bb;
         }
         unsigned long long pend = __ballot(bl >= 0);
@@ -1171,8 +1187,9 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
             const int src = __ffsll((long long)pend) - 1;
             pend &= pend - 1;
             const int b = __shfl(bl, src);
-            const int x = (b % nb1) * 4 + (lane & 3), y = ((b / nb1) % nb1) * 4 + ((lane >> 2) & 3),
-                      z = (b / (nb1 * nb1)) * 4 + (lane >> 4);
+            const int x = bx_of((uint32_t)b) * 4 + (lane & 3), y = by_of((uint32_t)b) * 4 + ((lane >> 2) & 3),
+                      z = bz_of((uint32_t)b) * 4 + (lane >> 4);
+            const int bi = blin((uint32_t)b, nb1);
             uint32_t qc[8];
             corner_index(n, nn, x, y, z, qc);
             const uint32_t q = qc[0];
@@ -1194,9 +1211,9 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
             const int cnt = __popcll(bal);
             nq += cnt;
             np += cnt;
-            delta += (long long)cnt - (long long)a.w.bcnt[b];
+            delta += (long long)cnt - (long long)a.w.bcnt[bi];
             __syncthreads();
-            if (lane == 0) a.w.bcnt[b] = (uint32_t)cnt;
+            if (lane == 0) a.w.bcnt[bi] = (uint32_t)cnt;
             if (classify) {
                 nq = 0;
             } else if (nq >= 64) {
