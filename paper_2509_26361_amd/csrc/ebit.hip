@@ -913,9 +913,10 @@ __device__ __forceinline__ T cell_volume(const uint8_t f[8], int has, const T sv
         Pt<T> S = {T(0), T(0), T(0)};
         T A1[3] = {T(0), T(0), T(0)};
         int four = 0;
-        // segments kept for the multi-loop path: start/end edge ids
+        // segments kept for the multi-loop path: start/end edge ids, one byte
+        // (start | end << 4) per segment in two words (registers, not scratch)
         int segs = 0;
-        uint8_t sst[12], sen[12];
+        uint64_t sg[2] = {0, 0};
 #pragma unroll
         for (int fc = 0; fc < 6; ++fc) {
             int cl[4], mk[4], ex[4], ed[4];
@@ -982,8 +983,11 @@ __device__ __forceinline__ T cell_volume(const uint8_t f[8], int has, const T sv
                     for (int id = 0; id < 12; ++id)
                         if (((lab >> (4 * id)) & 15) == drop) lab = (lab & ~(15ull << (4 * id))) | (keep << (4 * id));
                 }
-                sst[segs] = (uint8_t)is;
-                sen[segs] = (uint8_t)ie;
+                {
+                    const uint64_t v = (uint64_t)(is | (ie << 4)) << (8 * (segs & 7));
+                    if (segs < 8) sg[0] |= v;
+                    else sg[1] |= v;
+                }
                 ++segs;
             }
             if (kTab.upper[fc]) {
@@ -1029,7 +1033,8 @@ __device__ __forceinline__ T cell_volume(const uint8_t f[8], int has, const T sv
                 gx = gx / (T)nm; gy = gy / (T)nm; gz = gz / (T)nm;
                 Pt<T> Sr = {T(0), T(0), T(0)};
                 for (int k = 0; k < segs; ++k) {
-                    int is = sst[k], ie = sen[k];
+                    const uint64_t w = k < 8 ? sg[0] : sg[1];
+                    const int is = (int)((w >> (8 * (k & 7))) & 15), ie = (int)((w >> (8 * (k & 7) + 4)) & 15);
                     if (((lab >> (4 * is)) & 15) != (uint64_t)r) continue;
                     T ss = T(0), se = T(0);
 #pragma unroll
