@@ -33,10 +33,40 @@ MLP_GRAD_FLOP = MLP_FWD_FLOP + 2 * (2 * 128 * 128 + 20 * 128 + 128)
 # algorithmic bytes per interfacial cell (FP64 / FP32 storage):
 #   sweep: read s_x,s_y,s_z + flags + U_d, write s_x,s_y,s_z + flags
 #   Front2VOF: read s_x,s_y,s_z + flags, write C
+#   Front2VOF with the next x sweep (one launch): both
 BYTES = {
     "fp64": {"sweep": 3 * 8 + 1 + 8 + 3 * 8 + 1, "f2v": 3 * 8 + 1 + 8},
     "fp32": {"sweep": 3 * 4 + 1 + 4 + 3 * 4 + 1, "f2v": 3 * 4 + 1 + 4},
 }
+for _b in BYTES.values():
+    _b["fused"] = _b["sweep"] + _b["f2v"]
+# launch kinds timed by the library: kernel name (traffic key), description
+KERNELS = {
+    "sweep": ("k_sweep", "k_sweep (ebit_advect_sweep)"),
+    "f2v": ("k_f2v", "k_f2v (ebit_front2vof)"),
+    "fused": ("k_f2v_sweep_x", "k_f2v_sweep_x (ebit_advance: Front2VOF + next x sweep)"),
+}
+
+
+def launch_times(tm):
+    """(timed launches, seconds) per launch kind from Ebit.timing()."""
+    return {"sweep": (tm["sweeps"], tm["sweep_ms"] * 1e-3), "f2v": (tm["f2v"], tm["f2v_ms"] * 1e-3),
+            "fused": (tm["fused"], tm["fused_ms"] * 1e-3)}
+
+
+def roofline(kt, units, precision, workload):
+    """Roofline entry of the launch kind with the largest timed total:
+    algorithmic bytes (per interfacial cell x cells per launch) over its mean
+    launch duration."""
+    tot = {k: v[1] for k, v in kt.items()}
+    dom = max(tot, key=tot.get)
+    avg_dur = tot[dom] / max(1, kt[dom][0])
+    achieved = BYTES[precision][dom] * units / avg_dur / 1e9
+    return {"kernel": KERNELS[dom][1], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": stored_traffic(KERNELS[dom][0], workload, precision),
+            "bytes_per_unit": BYTES[precision][dom], "units_per_launch": units,
+            "avg_launch_us": avg_dur * 1e6, "timed_launches": kt[dom][0]}
 
 
 def parse():
@@ -125,7 +155,7 @@ def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8):
     step = W + K
     st1 = e.stats(C)
     n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
-    kt = {"sweep": (tm["sweeps"], tm["sweep_ms"] * 1e-3), "f2v": (tm["f2v"], tm["f2v_ms"] * 1e-3)}
+    kt = launch_times(tm)
     return {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "kt": kt, "C": C.double(),
             "C0": C0.double(), "ended_at_T": step == int(round(T_end / dt))}
 
@@ -161,12 +191,7 @@ def main():
     r = run_case(E, I, torch, n, a.precision, W, K, events=True, every=a.timing_every)
     wall, n_start, st0, st1, kt = r["wall"], r["n_start"], r["st0"], r["st1"], r["kt"]
     value = n_start / wall
-    tot = {k: v[1] for k, v in kt.items()}
-    dom = max(tot, key=tot.get)
-    avg_dur = tot[dom] / max(1, kt[dom][0])
     units_per_launch = n_start / K          # interfacial cells per launch (step-start count)
-    bytes_per_launch = BYTES[a.precision][dom] * units_per_launch
-    achieved = bytes_per_launch / avg_dur / 1e9
     e_shape = float((r["C"] - r["C0"]).abs().sum() / r["C0"].sum())
 
     out = {
@@ -185,19 +210,7 @@ def main():
         "config": {"workload": f"deformation_{n}: sphere R=0.15 at 0.35, LeVeque field x cos(pi t/3), "
                                f"CFL 0.5, steps {W}..{W + K} of {period}",
                    "n": n, "precision": a.precision, "sweeps_per_step": 3},
-        "roofline": {
-            "kernel": "k_sweep (ebit_advect_sweep)" if dom == "sweep" else "k_f2v (ebit_front2vof)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": stored_traffic("k_sweep" if dom == "sweep" else "k_f2v", n, a.precision),
-            "bytes_per_unit": BYTES[a.precision][dom],
-            "units_per_launch": units_per_launch,
-            "avg_launch_us": avg_dur * 1e6,
-            "timed_launches": kt[dom][0],
-        },
+        "roofline": roofline(kt, units_per_launch, a.precision, n),
         "launch_us": {k: (kt[k][1] / kt[k][0] * 1e6 if kt[k][0] else None) for k in kt},
         "interfacial_cells": {"start": st0["n_interfacial"], "end": st1["n_interfacial"],
                               "mean": n_start / K},
@@ -352,7 +365,7 @@ def mixed_case(E, I, torch, n, precision, W, K, phi, pf, U64, every, theta=None)
     st1 = e.stats(C)
     n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
     res = {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "C": C,
-           "kt": {"sweep": (tm["sweeps"], tm["sweep_ms"] * 1e-3), "f2v": (tm["f2v"], tm["f2v_ms"] * 1e-3)}}
+           "kt": launch_times(tm)}
     del e, Ud
     return res
 
@@ -378,11 +391,7 @@ def run_mixed(a, E, I, torch):
     log("fp64 run")
     r = mixed_case(E, I, torch, n, "fp64", W, K, phi, pf, U, a.timing_every)
     kt = r["kt"]
-    tot = {k: v[1] for k, v in kt.items()}
-    dom = max(tot, key=tot.get)
-    avg_dur = tot[dom] / max(1, kt[dom][0])
     units = r["n_start"] / K
-    achieved = BYTES["fp64"][dom] * units / avg_dur / 1e9
     V64 = r["st1"]["volume"] + r["st1"]["volume_comp"]
     out = {
         "metric": "interfacial cell-updates/s (advect+Front2VOF), 512^3 mixed run; vol err vs FP64",
@@ -394,12 +403,7 @@ def run_mixed(a, E, I, torch):
         "config": {"workload": f"mixed_512: {len(rs)} random spheres r U(3,12) cells, gap 2 cells, random "
                                f"divergence-free Fourier field (8 modes/component, max|u| = 1), CFL 0.5, "
                                f"steps {W}..{W + K}", "n": n, "precision": "fp64", "sweeps_per_step": 3},
-        "roofline": {"kernel": "k_sweep (ebit_advect_sweep)" if dom == "sweep" else "k_f2v (ebit_front2vof)",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic("k_sweep" if dom == "sweep" else "k_f2v", "mixed_512", "fp64"),
-                     "bytes_per_unit": BYTES["fp64"][dom], "units_per_launch": units,
-                     "avg_launch_us": avg_dur * 1e6, "timed_launches": kt[dom][0]},
+        "roofline": roofline(kt, units, "fp64", "mixed_512"),
         "launch_us": {k: (kt[k][1] / kt[k][0] * 1e6 if kt[k][0] else None) for k in kt},
         "interfacial_cells": {"start": r["st0"]["n_interfacial"], "end": r["st1"]["n_interfacial"], "mean": units},
         "volume": {"start": r["st0"]["volume"] + r["st0"]["volume_comp"], "end": V64},

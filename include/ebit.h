@@ -148,7 +148,10 @@ int ebit_current(const ebit_ctx *ctx);
  * `nsteps` steps of the hot path, launched from the library: per step k the
  * sweeps along x, y and z (ebit_advect_sweep with time factor g[k] and step
  * dt, the time level of the step for all three, sec. 2.3), then Front2VOF
- * into C (ebit_front2vof) unless C is NULL.
+ * into C (ebit_front2vof) unless C is NULL.  With EBIT_OPT_FUSE on (the
+ * default) and no surrogate set, the Front2VOF of step k < nsteps - 1 runs
+ * in one launch with the x sweep of step k + 1 (same results; C is complete
+ * when the enqueued work ends).
  *   U       3 device pointers: U_x, U_y, U_z (n^3 each, the precision's type)
  *   g       host array of nsteps time factors
  * Returns the first error of the calls it makes (the steps before it are
@@ -160,8 +163,10 @@ int ebit_advance(ebit_ctx *ctx, int32_t nsteps, const void *const *U, const doub
 /* Option switches. */
 enum {
     EBIT_OPT_FULL_GRID = 1,   /* 1: process every cell, not only the band */
-    EBIT_OPT_TIMING = 2       /* k > 0: bracket every k-th sweep launch and every k-th Front2VOF launch
-                                 with HIP events on its stream; 0: off */
+    EBIT_OPT_TIMING = 2,      /* k > 0: bracket every k-th launch of each kind (sweep, Front2VOF,
+                                 Front2VOF with an x sweep) with HIP events on its stream; 0: off */
+    EBIT_OPT_FUSE = 3         /* 1 (default): ebit_advance fuses a Front2VOF with the next x sweep;
+                                 0: separate launches */
 };
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
 
@@ -173,6 +178,8 @@ typedef struct {
     double sweep_ms;        /* their summed duration */
     int64_t f2v;            /* timed Front2VOF launches (the surrogate's included) */
     double f2v_ms;
+    int64_t fused;          /* timed launches of a Front2VOF with the next x sweep (ebit_advance) */
+    double fused_ms;
 } ebit_timing_t;
 
 /* Read and reset the accumulated launch times.  Synchronises with the last

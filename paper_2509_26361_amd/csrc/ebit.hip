@@ -105,8 +105,8 @@ struct Work {
     uint32_t *bchg;      // last sweep at which brick b was not quiet (see k_sweep)
     uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of nb entries
     uint32_t *bnum;      // [4][kSub] sub-list lengths
-    uint32_t *flist[2];  // revisit list of generation g: flist[g % 2]
-    uint32_t *fnum;      // [2][kSub]
+    uint32_t *flist[3];  // revisit list of generation g: flist[g % 3]
+    uint32_t *fnum;      // [3][kSub]
     uint32_t *ctask;     // per wave segcap interfacial cells of the last Front2VOF
     uint32_t *ccnt;      // [nw] their counts
     unsigned long long *cs;     // [CS_COUNT][nw] per-wave counters
@@ -132,8 +132,8 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(nb * 4); if (w) w->bchg = (uint32_t *)p;
     for (int k = 0; k < 4; ++k) { p = take(kSub * nb * 4); if (w) w->blist[k] = (uint32_t *)p; }
     p = take(4 * kSub * 4); if (w) w->bnum = (uint32_t *)p;
-    for (int k = 0; k < 2; ++k) { p = take(kSub * nb * 4); if (w) w->flist[k] = (uint32_t *)p; }
-    p = take(2 * kSub * 4); if (w) w->fnum = (uint32_t *)p;
+    for (int k = 0; k < 3; ++k) { p = take(kSub * nb * 4); if (w) w->flist[k] = (uint32_t *)p; }
+    p = take(3 * kSub * 4); if (w) w->fnum = (uint32_t *)p;
     p = take(nw * seg * 4); if (w) w->ctask = (uint32_t *)p;
     p = take(nw * 4); if (w) w->ccnt = (uint32_t *)p;
     p = take(CS_COUNT * nw * 8); if (w) w->cs = (unsigned long long *)p;
@@ -384,7 +384,7 @@ __global__ void k_zero_work(Work w, Geo g)
         w.bchg[i] = 0;
     }
     if (i < 4 * kSub) w.bnum[i] = 0;
-    if (i < 2 * kSub) w.fnum[i] = 0;
+    if (i < 3 * kSub) w.fnum[i] = 0;
     if (i < g.nw) {
         w.ccnt[i] = 0;
         for (int k = 0; k < CS_COUNT; ++k) w.cs[k * g.nw + i] = 0;
@@ -477,7 +477,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
 // join the next sweep's list; bricks whose cells change join the next
 // Front2VOF's list.
 template <typename T, int D>
-__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
+__device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, const int nw)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     __shared__ uint8_t tfl[kBatch][kATile];
@@ -487,14 +487,13 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap];
     const int lane = threadIdx.x;
-    const int wv = blockIdx.x, nw = gridDim.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const uint32_t t = a.t;
     const uint32_t *cm_cur = a.w.cm[t % 3];
     uint32_t *cm_next = a.w.cm[(t + 1) % 3];
     const int sub = wv % kSub;
     uint32_t *lnext = a.w.blist[(t + 1) % 4], *nnext = a.w.bnum + ((t + 1) % 4) * kSub;
-    uint32_t *lrev = a.w.flist[a.fgen % 2], *nrev = a.w.fnum + (a.fgen % 2) * kSub;
+    uint32_t *lrev = a.w.flist[a.fgen % 3], *nrev = a.w.fnum + (a.fgen % 3) * kSub;
     if (wv == 0 && lane < kSub) a.w.bnum[((t + 2) % 4) * kSub + lane] = 0;   // sweep t+2's list starts empty
     const long str[3] = {1, (long)n, a.g.nn};
     const int lu[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
@@ -816,6 +815,12 @@ __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
         a.w.cs[CS_MERGED * nwv + wv] += (unsigned long long)mergedc;
         a.w.cs[CS_ACTIVE * nwv + wv] += (unsigned long long)nact * 64ull;
     }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
+{
+    sweep_wave<T, D>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1155,21 +1160,22 @@ __device__ __forceinline__ int f2v_cells(const F2VArgs<T> &a, const uint32_t *cq
 // the surrogate and its training rows).  With `classify` set only the
 // segment is written for the interfacial cells.
 template <typename T>
-__global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int classify)
+__device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify, const int wv, const int nw)
 {
     __shared__ uint32_t cq[kCellCap];
     __shared__ uint64_t cf[kCellCap];
     const int lane = threadIdx.x;
-    const int wv = blockIdx.x, nw = gridDim.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const long nn = a.g.nn;
     const uint32_t gen = a.gen;
-    if (wv == 0 && lane < kSub) a.w.fnum[((gen + 1) % 2) * kSub + lane] = 0;   // the next generation starts empty
+    // generation gen + 2 starts empty (gen - 1's Front2VOF has ended; the
+    // sweeps writing gen + 1's list may run beside this one)
+    if (wv == 0 && lane < kSub) a.w.fnum[((gen + 2) % 3) * kSub + lane] = 0;
     Items it;
     if (a.full) {
         it.total = (uint32_t)nb;
     } else {
-        it.init(a.w.fnum + (gen % 2) * kSub, nullptr, a.w.flist[gen % 2], nullptr, (uint32_t)nb);
+        it.init(a.w.fnum + (gen % 3) * kSub, nullptr, a.w.flist[gen % 3], nullptr, (uint32_t)nb);
     }
     uint32_t *seg = a.w.ctask + (size_t)wv * a.g.segcap;
     long np = 0;
@@ -1244,6 +1250,25 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
         a.w.cs[CS_INTER_SUM * nwv + wv] += cur;
         if (!classify) a.w.cs[CS_AMB * nwv + wv] = (unsigned long long)ambc;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int classify)
+{
+    f2v_wave<T>(a, classify, blockIdx.x, gridDim.x);
+}
+
+// A Front2VOF and the x sweep that follows it, in one grid: the sweep reads
+// the state the Front2VOF reads and writes the other buffer, so the two are
+// independent.  The sweep's workgroups come first and fill the chip; the
+// Front2VOF's start as sweep waves retire and fill the sweep's tail (both
+// parts have a multiple of 8 waves, so each keeps its XCD-aware mapping).
+template <typename T>
+__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_f2v_sweep_x(SweepArgs<T> s, F2VArgs<T> f)
+{
+    const int b = blockIdx.x, nw = s.g.nw;
+    if (b < nw) sweep_wave<T, 0>(s, b, nw);
+    else f2v_wave<T>(f, 0, b - nw, nw);
 }
 
 
@@ -1543,11 +1568,12 @@ struct ebit_ctx {
     int full;              // process every brick
     const void *lastC;     // C array of the previous Front2VOF
     const float *surr;     // surrogate parameters (NULL: geometric Front2VOF only)
+    int fuse;              // ebit_advance launches a Front2VOF with the next x sweep
     int timing;            // bracket every timing-th launch of each kind with events (0: off)
-    unsigned tseen[2];     // launches of each kind since timing was switched on
+    unsigned tseen[3];     // launches of each kind since timing was switched on
     int tsel;              // the current launch is bracketed
     hipEvent_t *ev;        // 2 * kTimed events
-    uint8_t *ev_kind;      // 0 sweep, 1 Front2VOF
+    uint8_t *ev_kind;      // 0 sweep, 1 Front2VOF, 2 Front2VOF with the x sweep
     int ev_n;              // launches recorded since the last ebit_timing
 };
 
@@ -1588,8 +1614,8 @@ void time_end(ebit_ctx *c, hipStream_t st, int kind)
     c->tsel = 0;
 }
 
-template <typename T, int D>
-void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
+template <typename T>
+SweepArgs<T> sweep_args(const ebit_ctx *c, const void *U, T cf)
 {
     SweepArgs<T> a;
     a.g = c->g;
@@ -1605,9 +1631,30 @@ void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
     a.t = c->t;
     a.fgen = c->fgen;
     a.full = c->full;
+    return a;
+}
+
+template <typename T, int D>
+void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
+{
+    const SweepArgs<T> a = sweep_args<T>(c, U, cf);
     time_begin(c, st, 0);
     hipLaunchKernelGGL((k_sweep<T, D>), dim3(c->g.nw), dim3(64), 0, st, a);
     time_end(c, st, 0);
+}
+
+template <typename T>
+F2VArgs<T> f2v_args(const ebit_ctx *c, void *C, int full)
+{
+    F2VArgs<T> a;
+    a.g = c->g;
+    a.fl = c->flags[c->cur];
+    for (int e = 0; e < 3; ++e) a.s[e] = (const T *)c->s[c->cur][e];
+    a.C = (T *)C;
+    a.w = c->w;
+    a.gen = c->fgen;
+    a.full = full;
+    return a;
 }
 
 template <typename T>
@@ -1628,14 +1675,7 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
 {
     int full = c->full || C != c->lastC;
     if (!full && c->last_t_f2v == c->t) return EBIT_OK;   // nothing moved since the last call
-    F2VArgs<T> a;
-    a.g = c->g;
-    a.fl = c->flags[c->cur];
-    for (int e = 0; e < 3; ++e) a.s[e] = (const T *)c->s[c->cur][e];
-    a.C = (T *)C;
-    a.w = c->w;
-    a.gen = c->fgen;
-    a.full = full;
+    const F2VArgs<T> a = f2v_args<T>(c, C, full);
     time_begin(c, st, 1);
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
@@ -1644,6 +1684,24 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     c->fgen++;
     c->last_t_f2v = c->t;
     c->lastC = C;
+    return check_launch();
+}
+
+// Front2VOF into C (geometric, after at least one sweep) and then the x sweep
+// of the next step, as one launch of k_f2v_sweep_x.
+template <typename T>
+int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, hipStream_t st)
+{
+    const F2VArgs<T> f = f2v_args<T>(c, C, c->full || C != c->lastC);
+    c->fgen++;
+    c->last_t_f2v = c->t;
+    c->lastC = C;
+    const SweepArgs<T> a = sweep_args<T>(c, Ux, (T)((dt * (double)c->n) * g));
+    time_begin(c, st, 2);
+    hipLaunchKernelGGL((k_f2v_sweep_x<T>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
+    time_end(c, st, 2);
+    c->t++;
+    c->cur ^= 1;
     return check_launch();
 }
 
@@ -1747,6 +1805,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->full = 0;
     c->lastC = nullptr;
     c->surr = nullptr;
+    c->fuse = 1;
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
@@ -1877,7 +1936,11 @@ int ebit_set_option(ebit_ctx *c, int option, int value)
             c->ev_n = 0;
         }
         c->timing = value > 0 ? value : 0;
-        c->tseen[0] = c->tseen[1] = 0;
+        c->tseen[0] = c->tseen[1] = c->tseen[2] = 0;
+        return EBIT_OK;
+    }
+    if (option == EBIT_OPT_FUSE) {
+        c->fuse = value != 0;
         return EBIT_OK;
     }
     return EBIT_EINVAL;
@@ -1893,7 +1956,8 @@ int ebit_timing(ebit_ctx *c, ebit_timing_t *out)
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess) return EBIT_EHIP;
         if (c->ev_kind[k] == 0) { out->sweeps++; out->sweep_ms += ms; }
-        else { out->f2v++; out->f2v_ms += ms; }
+        else if (c->ev_kind[k] == 1) { out->f2v++; out->f2v_ms += ms; }
+        else { out->fused++; out->fused_ms += ms; }
     }
     c->ev_n = 0;
     return EBIT_OK;
@@ -1903,14 +1967,30 @@ int ebit_advance(ebit_ctx *c, int32_t nsteps, const void *const *U, const double
                  void *stream)
 {
     if (!c || nsteps < 0 || !U || !U[0] || !U[1] || !U[2] || (nsteps > 0 && !g)) return EBIT_EINVAL;
+    // a Front2VOF due before the next x sweep goes into that sweep's launch
+    // (geometric Front2VOF only: the surrogate's second pass needs the first)
+    const int fuse = C && c->fuse && !c->surr;
+    int pending = 0;
     for (int k = 0; k < nsteps; ++k) {
         for (int d = 0; d < 3; ++d) {
-            int rc = ebit_advect_sweep(c, d, U[d], g[k], dt, stream);
+            int rc;
+            if (d == 0 && pending) {
+                if (!(dt >= 0.0) || !isfinite(g[k])) return EBIT_EINVAL;
+                rc = c->precision == EBIT_FP64 ? f2v_sweep_x_impl<double>(c, C, U[0], g[k], dt, S(stream))
+                                               : f2v_sweep_x_impl<float>(c, C, U[0], g[k], dt, S(stream));
+                pending = 0;
+            } else {
+                rc = ebit_advect_sweep(c, d, U[d], g[k], dt, stream);
+            }
             if (rc != EBIT_OK) return rc;
         }
         if (C) {
-            int rc = ebit_front2vof(c, C, stream);
-            if (rc != EBIT_OK) return rc;
+            if (fuse && k + 1 < nsteps) {
+                pending = 1;
+            } else {
+                int rc = ebit_front2vof(c, C, stream);
+                if (rc != EBIT_OK) return rc;
+            }
         }
     }
     return EBIT_OK;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libebit.so")
 
 EBIT_OK, EBIT_EINVAL, EBIT_ECFL, EBIT_ESTATE, EBIT_EHIP, EBIT_ENOSURR, EBIT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 EBIT_FP64, EBIT_FP32 = 0, 1
-EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING = 1, 2
+EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING, EBIT_OPT_FUSE = 1, 2, 3
 
 _lib = None
 
@@ -40,7 +40,8 @@ class Desc(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("sweep_ms", ctypes.c_double),
-                ("f2v", ctypes.c_int64), ("f2v_ms", ctypes.c_double)]
+                ("f2v", ctypes.c_int64), ("f2v_ms", ctypes.c_double),
+                ("fused", ctypes.c_int64), ("fused_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -214,7 +215,8 @@ class Ebit:
 
     def advance(self, Uxyz, g, dt: float, C=None, stream=None):
         """len(g) steps (sweeps x, y, z with time factor g[k], then Front2VOF
-        into C unless None), launched by the library."""
+        into C unless None), launched by the library (a Front2VOF and the next
+        x sweep in one launch unless EBIT_OPT_FUSE is off)."""
         gs = (ctypes.c_double * max(1, len(g)))(*[float(v) for v in g])
         U = (ctypes.c_void_p * 3)(*[_ptr(u) for u in Uxyz])
         rc = lib().ebit_advance(self.ctx, len(g), U, gs, float(dt), _ptr(C) if C is not None else None,

@@ -238,39 +238,58 @@ def test_courant_violation_is_reported():
     assert ex.value.code == E.EBIT_ECFL
 
 
-def test_advance_equals_single_calls_and_timing():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_advance_equals_single_calls_and_timing(prec):
     """ebit_advance = the same sweeps and Front2VOF issued one call at a time
-    (bit-exact), and the timing option counts every launch."""
+    (bit-exact), with each Front2VOF fused into the next x sweep's launch or
+    not, and split over several calls that switch to a new C array; the
+    timing option counts every launch of each kind."""
     n = 32
     sh = I.sphere_shape(n, centre=(0.45, 0.5, 0.55), R=0.2)
-    U = [T(u) for u in I.deformation_velocity(n)]
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    U = [T(u).to(dtype) for u in I.deformation_velocity(n)]
     dt = 0.5 / n
     gs = [I.deformation_time_factor(k * dt, 3.0) for k in range(12)]
     runs = []
-    for mode in ("calls", "advance"):
-        e = E.Ebit(n, "fp64", dev())
+    for mode in ("calls", "fused", "unfused", "split"):
+        e = E.Ebit(n, prec, dev())
         e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
-        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        C = torch.zeros((n, n, n), dtype=dtype, device=dev())
         if mode == "calls":
             for g in gs:
                 e.step(U, g, dt)
                 e.front2vof(C)
+        elif mode == "split":
+            # a first C array, then C: each first Front2VOF into an array
+            # recomputes every cell (in a fused launch for C)
+            C0 = torch.zeros_like(C)
+            e.advance(U, gs[:5], dt, C0)
+            e.advance(U, gs[5:7], dt, C)
+            e.advance(U, gs[7:8], dt, C)
+            e.advance(U, gs[8:], dt, C)
         else:
             e.set_option(E.EBIT_OPT_TIMING, 1)
+            e.set_option(E.EBIT_OPT_FUSE, 1 if mode == "fused" else 0)
             e.advance(U, gs, dt, C)
             tm = e.timing()
-            assert tm["sweeps"] == 3 * len(gs) and tm["f2v"] == len(gs)
+            if mode == "fused":
+                assert tm["sweeps"] == 3 * len(gs) - (len(gs) - 1) and tm["fused"] == len(gs) - 1
+                assert tm["f2v"] == 1 and tm["fused_ms"] > 0
+            else:
+                assert tm["sweeps"] == 3 * len(gs) and tm["f2v"] == len(gs) and tm["fused"] == 0
             assert tm["sweep_ms"] > 0 and tm["f2v_ms"] > 0
             assert e.timing()["sweeps"] == 0
         torch.cuda.synchronize()
         fl, s = e.state()
-        runs.append((fl.cpu().numpy(), [x.cpu().numpy() for x in s], C.cpu().numpy(), e.stats(C)))
-    (f0, s0, c0, st0), (f1, s1, c1, st1) = runs
-    assert np.array_equal(f0, f1)
-    for k in range(3):
-        assert np.array_equal(s0[k], s1[k])
-    assert np.array_equal(c0, c1)
-    assert st0["n_interfacial_sum"] == st1["n_interfacial_sum"]
+        runs.append((mode, fl.cpu().numpy(), [x.cpu().numpy() for x in s], C.cpu().numpy(), e.stats(C)))
+    _, f0, s0, c0, st0 = runs[0]
+    for mode, f1, s1, c1, st1 in runs[1:]:
+        assert np.array_equal(f0, f1), mode
+        for k in range(3):
+            assert np.array_equal(s0[k], s1[k]), mode
+        assert np.array_equal(c0, c1), mode
+        assert st0["n_interfacial"] == st1["n_interfacial"], mode
+        assert st0["n_interfacial_sum"] == st1["n_interfacial_sum"], mode
 
 
 def test_timing_samples_every_kth_launch():
@@ -283,7 +302,8 @@ def test_timing_samples_every_kth_launch():
     e.set_option(E.EBIT_OPT_TIMING, 4)
     e.advance(U, [1.0] * 12, 0.5 / n, C)
     tm = e.timing()
-    assert tm["sweeps"] == 9 and tm["f2v"] == 3      # launches 0, 4, 8, ... of each kind
+    # launches 0, 4, 8, ... of each kind: 25 sweeps, 11 Front2VOF + x sweep, 1 Front2VOF
+    assert tm["sweeps"] == 7 and tm["fused"] == 3 and tm["f2v"] == 1
     e.set_option(E.EBIT_OPT_TIMING, 0)
     e.advance(U, [1.0] * 2, 0.5 / n, C)
     assert e.timing()["sweeps"] == 0
