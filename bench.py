@@ -83,7 +83,7 @@ def parse():
     p.add_argument("--no-fp32", action="store_true", help="skip the FP32 precision-form run")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-surrogate", action="store_true", help="skip training / running the learned Front2VOF")
-    p.add_argument("--surr-rows", type=int, default=2_000_000, help="training rows (unambiguous cells)")
+    p.add_argument("--surr-rows", type=int, default=10_000_000, help="training rows (unambiguous cells)")
     p.add_argument("--surr-steps", type=int, default=20000, help="Adam steps")
     p.add_argument("--surr-batch", type=int, default=8192)
     p.add_argument("--timing-every", type=int, default=32,

@@ -14,8 +14,10 @@
 // marker claims its 27 neighbours (an atomic exchange of a per-brick stamp
 // decides the one claimant) and appends the new ones, wave-aggregated, to one
 // of kSub sub-lists with a counter each (sub-list = wave id mod kSub), so no
-// single address takes every append.  The same scheme builds the list of
-// bricks that the next Front2VOF must revisit.
+// single address takes more than a few dozen appends per sweep (atomics on
+// one address serialise).  A sub-list holds twice its fair share; a brick
+// that finds it full goes to the list's overflow sub-list.  The same scheme
+// builds the list of bricks that the next Front2VOF must revisit.
 //
 // Waves.  Both kernels run one 64-lane wave per workgroup over a fixed grid
 // of nw waves; wave w takes list items w, w + nw, ... (balanced to one brick).
@@ -50,7 +52,15 @@ using namespace ebit;
 namespace {
 
 constexpr int kRedBlocks = 1024;
-constexpr int kSub = 16;          // sub-lists per brick list
+#ifndef EBIT_SUBLISTS
+#define EBIT_SUBLISTS 64
+#endif
+constexpr int kSub = EBIT_SUBLISTS;   // sub-lists per brick list (a power of two, at most 64)
+constexpr int kNum = kSub + 1;    // lengths per list: the sub-lists, then the overflow
+#ifndef EBIT_NUM_PAD
+#define EBIT_NUM_PAD 16
+#endif
+constexpr int kPad = EBIT_NUM_PAD; // lengths are kPad words apart: atomics on one cache line serialise
 #ifndef EBIT_MAX_WAVES
 #define EBIT_MAX_WAVES 3072
 #endif
@@ -80,6 +90,7 @@ struct Geo {
     int nb;         // bricks
     int nw;         // waves of the sweep / Front2VOF grids
     long segcap;    // interfacial-cell segment length per wave
+    int scap;       // entries per sub-list of a brick list
 };
 
 int waves_for(int n)
@@ -87,6 +98,13 @@ int waves_for(int n)
     const long nb = (long)(n / 4) * (n / 4) * (n / 4);
     const long w = nb < 64 ? 64 : (nb > kMaxWaves ? kMaxWaves : nb);
     return (int)(w & ~7L);      // a whole number of waves per XCD
+}
+
+// entries per sub-list of a brick list: twice the fair share of nb
+int scap_for(int n)
+{
+    const int nb = (n / 4) * (n / 4) * (n / 4);
+    return (2 * nb + kSub - 1) / kSub + 64;
 }
 
 // items per wave are at most ceil(nb / nw) + 2 under item_of()
@@ -103,10 +121,10 @@ struct Work {
     uint32_t *fmark;     // fmark[b] == g <=> brick b is in the revisit list of Front2VOF generation g
     uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
     uint32_t *bchg;      // last sweep at which brick b was not quiet (see k_sweep)
-    uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of nb entries
-    uint32_t *bnum;      // [4][kSub] sub-list lengths
+    uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of scap entries, overflow of nb
+    uint32_t *bnum;      // [4][kNum] sub-list lengths, kPad words apart
     uint32_t *flist[3];  // revisit list of generation g: flist[g % 3]
-    uint32_t *fnum;      // [3][kSub]
+    uint32_t *fnum;      // [3][kNum], kPad words apart
     uint32_t *ctask;     // per wave segcap interfacial cells of the last Front2VOF
     uint32_t *ccnt;      // [nw] their counts
     unsigned long long *cs;     // [CS_COUNT][nw] per-wave counters
@@ -130,10 +148,11 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(nb * 4); if (w) w->fmark = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bcnt = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bchg = (uint32_t *)p;
-    for (int k = 0; k < 4; ++k) { p = take(kSub * nb * 4); if (w) w->blist[k] = (uint32_t *)p; }
-    p = take(4 * kSub * 4); if (w) w->bnum = (uint32_t *)p;
-    for (int k = 0; k < 3; ++k) { p = take(kSub * nb * 4); if (w) w->flist[k] = (uint32_t *)p; }
-    p = take(3 * kSub * 4); if (w) w->fnum = (uint32_t *)p;
+    const size_t lsz = ((size_t)kSub * scap_for(n) + nb) * 4;
+    for (int k = 0; k < 4; ++k) { p = take(lsz); if (w) w->blist[k] = (uint32_t *)p; }
+    p = take(4 * kNum * kPad * 4); if (w) w->bnum = (uint32_t *)p;
+    for (int k = 0; k < 3; ++k) { p = take(lsz); if (w) w->flist[k] = (uint32_t *)p; }
+    p = take(3 * kNum * kPad * 4); if (w) w->fnum = (uint32_t *)p;
     p = take(nw * seg * 4); if (w) w->ctask = (uint32_t *)p;
     p = take(nw * 4); if (w) w->ccnt = (uint32_t *)p;
     p = take(CS_COUNT * nw * 8); if (w) w->cs = (unsigned long long *)p;
@@ -193,8 +212,21 @@ struct ClaimList {
     uint32_t *num;
 };
 
+// brick b at position q of sub-list `sub`, or in the overflow sub-list when
+// the sub-list is full
+__device__ __forceinline__ void list_put(const ClaimList &L, uint32_t q, uint32_t b, int sub, uint32_t scap,
+                                         uint32_t ocap)
+{
+    if (q < scap) {
+        L.list[(size_t)sub * scap + q] = b;
+        return;
+    }
+    const uint32_t o = atomicAdd(&L.num[kSub * kPad], 1u);
+    if (o < ocap) L.list[(size_t)kSub * scap + o] = b;
+}
+
 __device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const uint32_t *srcB, int nbr, int nb1,
-                                          ClaimList A, ClaimList B, int sub, uint32_t cap)
+                                          ClaimList A, ClaimList B, int sub, uint32_t scap, uint32_t ocap)
 {
     const int lane = threadIdx.x & 63;
     const int ta = na * 27, total = ta + nbr * 8;
@@ -233,16 +265,16 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const ui
             cB += __popcll(balB[u]);
         }
         uint32_t pA = 0, pB = 0;
-        if (lane == 0 && cA) pA = atomicAdd(&A.num[sub], (uint32_t)cA);
-        if (lane == 0 && cB) pB = atomicAdd(&B.num[sub], (uint32_t)cB);
+        if (lane == 0 && cA) pA = atomicAdd(&A.num[sub * kPad], (uint32_t)cA);
+        if (lane == 0 && cB) pB = atomicAdd(&B.num[sub * kPad], (uint32_t)cB);
         pA = __shfl(pA, 0);
         pB = __shfl(pB, 0);
         const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t qa = pA + (uint32_t)__popcll(balA[u] & lt), qb = pB + (uint32_t)__popcll(balB[u] & lt);
-            if (take[u] && inA[u] && qa < cap) A.list[(size_t)sub * cap + qa] = nbk[u];
-            if (take[u] && !inA[u] && qb < cap) B.list[(size_t)sub * cap + qb] = nbk[u];
+            if (take[u] && inA[u]) list_put(A, qa, nbk[u], sub, scap, ocap);
+            if (take[u] && !inA[u]) list_put(B, qb, nbk[u], sub, scap, ocap);
             pA += (uint32_t)__popcll(balA[u]);
             pB += (uint32_t)__popcll(balB[u]);
         }
@@ -263,39 +295,52 @@ __device__ __forceinline__ uint32_t item_of(uint32_t w, uint32_t i, uint32_t nw)
     return ((idx / kXcdChunk) * 8u + x) * kXcdChunk + idx % kXcdChunk;
 }
 
-// Items of a grid: the concatenation of up to two lists of kSub sub-lists
-// (lane j < 2 kSub holds the length and inclusive prefix of sub-list j).
+// Items of a grid: the concatenation of up to two lists, each its kSub
+// sub-lists and then its overflow sub-list.  The inclusive prefixes of the
+// sub-list lengths of both lists are kept in LDS (pre[0..kSub) and
+// pre[kSub..2 kSub)).
 struct Items {
-    uint32_t len, incl, total, nfirst;
+    uint32_t s0, s1;        // items in the sub-lists of list 0 / of list 1
+    uint32_t total, nfirst; // all items; items of list 0
     const uint32_t *l0, *l1;
-    uint32_t cap;
-    __device__ __forceinline__ void init(const uint32_t *num0, const uint32_t *num1, const uint32_t *list0,
-                                         const uint32_t *list1, uint32_t nb)
+    const uint32_t *pre;
+    uint32_t scap;
+    __device__ __forceinline__ void init(uint32_t *lds, const uint32_t *num0, const uint32_t *num1,
+                                         const uint32_t *list0, const uint32_t *list1, uint32_t scap_, uint32_t ocap)
     {
         const int lane = threadIdx.x & 63;
-        len = 0;
-        if (lane < kSub) len = min(num0[lane], nb);
-        else if (num1 && lane < 2 * kSub) len = min(num1[lane - kSub], nb);
-        incl = wave_incl_scan(len);
-        total = __shfl(incl, 63);
-        nfirst = __shfl(incl, kSub - 1);
+        const uint32_t inc0 = wave_incl_scan(lane < kSub ? min(num0[lane * kPad], scap_) : 0u);
+        const uint32_t inc1 = num1 ? wave_incl_scan(lane < kSub ? min(num1[lane * kPad], scap_) : 0u) : 0u;
+        if (lane < kSub) {
+            lds[lane] = inc0;
+            lds[kSub + lane] = inc1;
+        }
+        s0 = __shfl(inc0, kSub - 1);
+        nfirst = s0 + min(num0[kSub * kPad], ocap);
+        s1 = num1 ? __shfl(inc1, kSub - 1) : 0u;
+        total = num1 ? nfirst + s1 + min(num1[kSub * kPad], ocap) : nfirst;
         l0 = list0;
         l1 = list1;
-        cap = nb;
+        pre = lds;
+        scap = scap_;
+        __syncthreads();
     }
-    // brick of item k < total, a different k per lane (every lane must call)
+    // brick of item k < total, a different k per lane
     __device__ __forceinline__ int brick_lane(uint32_t k) const
     {
+        const bool second = k >= nfirst;
+        const uint32_t kk = second ? k - nfirst : k;
+        const uint32_t ns = second ? s1 : s0;
+        const uint32_t *l = second ? l1 : l0;
+        if (kk >= ns) return (int)l[(size_t)kSub * scap + (kk - ns)];   // overflow sub-list
+        // j = the sub-lists that end at or before kk (binary search)
+        const uint32_t *p = pre + (second ? kSub : 0);
         int j = 0;
-        uint32_t excl = 0;
 #pragma unroll
-        for (int m = 0; m < 2 * kSub; ++m) {
-            const uint32_t im = __shfl(incl, m);
-            if (im <= k) { j = m + 1; excl = im; }
-        }
-        if (j >= 2 * kSub) return -1;
-        const uint32_t *l = j < kSub ? l0 : l1;
-        return (int)l[(size_t)(j % kSub) * cap + (k - excl)];
+        for (int st = kSub / 2; st >= 1; st >>= 1)
+            if (p[j + st - 1] <= kk) j += st;
+        const uint32_t excl = j > 0 ? p[j - 1] : 0u;
+        return (int)l[(size_t)j * scap + (kk - excl)];
     }
 };
 
@@ -364,9 +409,9 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         long q = x + (long)g.n * y + g.nn * z;
         const bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
         if (hasm) {
-            const ClaimList A{w.cm[2], 2u, w.blist[2], w.bnum + 2 * kSub};
+            const ClaimList A{w.cm[2], 2u, w.blist[2], w.bnum + 2 * kNum * kPad};
             const uint32_t bp = bpack(bx, by, bz);
-            claim_two(&bp, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.nb);
+            claim_two(&bp, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap, (uint32_t)g.nb);
         }
     }
 }
@@ -383,8 +428,8 @@ __global__ void k_zero_work(Work w, Geo g)
         w.bcnt[i] = 0;
         w.bchg[i] = 0;
     }
-    if (i < 4 * kSub) w.bnum[i] = 0;
-    if (i < 3 * kSub) w.fnum[i] = 0;
+    if (i < 4 * kNum) w.bnum[i * kPad] = 0;
+    if (i < 3 * kNum) w.fnum[i * kPad] = 0;
     if (i < g.nw) {
         w.ccnt[i] = 0;
         for (int k = 0; k < CS_COUNT; ++k) w.cs[k * g.nw + i] = 0;
@@ -486,15 +531,17 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap];
+    __shared__ uint32_t ipre[2 * kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const uint32_t t = a.t;
     const uint32_t *cm_cur = a.w.cm[t % 3];
     uint32_t *cm_next = a.w.cm[(t + 1) % 3];
     const int sub = wv % kSub;
-    uint32_t *lnext = a.w.blist[(t + 1) % 4], *nnext = a.w.bnum + ((t + 1) % 4) * kSub;
-    uint32_t *lrev = a.w.flist[a.fgen % 3], *nrev = a.w.fnum + (a.fgen % 3) * kSub;
-    if (wv == 0 && lane < kSub) a.w.bnum[((t + 2) % 4) * kSub + lane] = 0;   // sweep t+2's list starts empty
+    uint32_t *lnext = a.w.blist[(t + 1) % 4], *nnext = a.w.bnum + ((t + 1) % 4) * kNum * kPad;
+    uint32_t *lrev = a.w.flist[a.fgen % 3], *nrev = a.w.fnum + (a.fgen % 3) * kNum * kPad;
+    if (wv == 0)   // sweep t+2's list starts empty
+        for (int i = lane; i < kNum; i += 64) a.w.bnum[(((t + 2) % 4) * kNum + i) * kPad] = 0;
     const long str[3] = {1, (long)n, a.g.nn};
     const int lu[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
     const int tself = (lu[D] + 1) + kAD * (lu[A1] + kAA * lu[A2]);
@@ -527,15 +574,15 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
         it.total = (uint32_t)nb;
         it.nfirst = (uint32_t)nb;
     } else {
-        it.init(a.w.bnum + (t % 4) * kSub, a.w.bnum + ((t + 3) % 4) * kSub, a.w.blist[t % 4],
-                a.w.blist[(t + 3) % 4], (uint32_t)nb);
+        it.init(ipre, a.w.bnum + (t % 4) * kNum * kPad, a.w.bnum + ((t + 3) % 4) * kNum * kPad, a.w.blist[t % 4],
+                a.w.blist[(t + 3) % 4], (uint32_t)a.g.scap, (uint32_t)nb);
     }
     int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0;
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
     auto claims = [&]() {
         __syncthreads();
         claim_two(mbr, nm, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
-                  ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)nb);
+                  ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)a.g.scap, (uint32_t)nb);
         __syncthreads();
         nm = 0;
         nc = 0;
@@ -1164,18 +1211,21 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
 {
     __shared__ uint32_t cq[kCellCap];
     __shared__ uint64_t cf[kCellCap];
+    __shared__ uint32_t ipre[2 * kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const long nn = a.g.nn;
     const uint32_t gen = a.gen;
     // generation gen + 2 starts empty (gen - 1's Front2VOF has ended; the
     // sweeps writing gen + 1's list may run beside this one)
-    if (wv == 0 && lane < kSub) a.w.fnum[((gen + 2) % 3) * kSub + lane] = 0;
+    if (wv == 0)
+        for (int i = lane; i < kNum; i += 64) a.w.fnum[(((gen + 2) % 3) * kNum + i) * kPad] = 0;
     Items it;
     if (a.full) {
         it.total = (uint32_t)nb;
     } else {
-        it.init(a.w.fnum + (gen % 3) * kSub, nullptr, a.w.flist[gen % 3], nullptr, (uint32_t)nb);
+        it.init(ipre, a.w.fnum + (gen % 3) * kNum * kPad, nullptr, a.w.flist[gen % 3], nullptr, (uint32_t)a.g.scap,
+                (uint32_t)nb);
     }
     uint32_t *seg = a.w.ctask + (size_t)wv * a.g.segcap;
     long np = 0;
@@ -1799,6 +1849,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->g.nb = nbricks;
     c->g.nw = waves_for(d->n);
     c->g.segcap = segcap_for(d->n);
+    c->g.scap = scap_for(d->n);
     c->t = 2;
     c->fgen = 1;
     c->last_t_f2v = 0;
@@ -1829,7 +1880,8 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
         free(c);
         return EBIT_EHIP;
     }
-    hipLaunchKernelGGL(k_zero_work, dim3((c->g.nb + 255) / 256), dim3(256), 0, st, c->w, c->g);
+    const int nz = c->g.nb > c->g.nw ? c->g.nb : (c->g.nw > 4 * kNum ? c->g.nw : 4 * kNum);
+    hipLaunchKernelGGL(k_zero_work, dim3((nz + 255) / 256), dim3(256), 0, st, c->w, c->g);
     hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, kMaxWaves)), dim3(64), 0, st, c->g, c->flags[0], c->w);
     int rc = check_launch();
     if (rc != EBIT_OK) {
