@@ -76,12 +76,12 @@ constexpr int kBatch = EBIT_BATCH;   // sweep: bricks staged together
 
 // totals reduced from the per-wave counters
 enum {
-    ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB,
+    ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM /* sum of gen * delta */, ST_INTER, ST_AMB,
     ST_MARK0, ST_MARK1, ST_MARK2, ST_COUNT = 16
 };
 // per-wave counters: cumulative over sweeps / Front2VOF calls, except the
 // last-Front2VOF one (CS_AMB)
-enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_SUM, CS_INTER, CS_AMB, CS_COUNT };
+enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_GEN, CS_INTER, CS_AMB, CS_COUNT };
 
 struct Geo {
     int n;
@@ -854,13 +854,14 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     cflc = wave_sum(cflc);
     mergedc = wave_sum(mergedc);
     multit = wave_sum(multit);
+    // (adds whose result is not waited for)
     if (lane == 0) {
         const int nwv = a.g.nw;
-        a.w.cs[CS_FALLBACK * nwv + wv] += (unsigned long long)fbc;
-        a.w.cs[CS_MULTI * nwv + wv] += (unsigned long long)multit;
-        a.w.cs[CS_CFL * nwv + wv] += (unsigned long long)cflc;
-        a.w.cs[CS_MERGED * nwv + wv] += (unsigned long long)mergedc;
-        a.w.cs[CS_ACTIVE * nwv + wv] += (unsigned long long)nact * 64ull;
+        if (fbc) atomicAdd(&a.w.cs[CS_FALLBACK * nwv + wv], (unsigned long long)fbc);
+        if (multit) atomicAdd(&a.w.cs[CS_MULTI * nwv + wv], (unsigned long long)multit);
+        if (cflc) atomicAdd(&a.w.cs[CS_CFL * nwv + wv], (unsigned long long)cflc);
+        if (mergedc) atomicAdd(&a.w.cs[CS_MERGED * nwv + wv], (unsigned long long)mergedc);
+        if (nact) atomicAdd(&a.w.cs[CS_ACTIVE * nwv + wv], (unsigned long long)nact * 64ull);
     }
 }
 
@@ -1295,9 +1296,13 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
     if (lane == 0) {
         const int nwv = a.g.nw;
         a.w.ccnt[wv] = (uint32_t)(np < a.g.segcap ? np : a.g.segcap);
-        const unsigned long long cur = (unsigned long long)((long long)a.w.cs[CS_INTER * nwv + wv] + delta);
-        a.w.cs[CS_INTER * nwv + wv] = cur;
-        a.w.cs[CS_INTER_SUM * nwv + wv] += cur;
+        // the interfacial count changes by delta at this generation; the sum
+        // over generations of the count follows from the sums of delta and
+        // gen * delta (adds whose result is not waited for)
+        if (delta) {
+            atomicAdd(&a.w.cs[CS_INTER * nwv + wv], (unsigned long long)delta);
+            atomicAdd(&a.w.cs[CS_INTER_GEN * nwv + wv], (unsigned long long)((long long)gen * delta));
+        }
         if (!classify) a.w.cs[CS_AMB * nwv + wv] = (unsigned long long)ambc;
     }
 }
@@ -1943,7 +1948,10 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     out->n_merged = (int64_t)stat[ST_MERGED];
     out->n_active_cells = (int64_t)stat[ST_ACTIVE];
     out->step_sweeps = (int64_t)(c->t - 2);
-    out->n_interfacial_sum = (int64_t)stat[ST_INTER_SUM];
+    // count after generation j: S1(j) = sum of delta up to j; summed over the
+    // generations 1..K so far: (K + 1) S1 - sum of j delta_j
+    const int64_t K = (int64_t)c->fgen - 1;
+    out->n_interfacial_sum = (K + 1) * (int64_t)stat[ST_INTER] - (int64_t)stat[ST_INTER_SUM];
     return out->n_cfl ? EBIT_ECFL : EBIT_OK;
 }
 
