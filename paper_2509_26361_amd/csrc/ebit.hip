@@ -5,10 +5,11 @@
 //
 // Band.  Work is restricted to 4x4x4-node bricks near the interface.  Sweep t
 // processes the bricks next to (26-neighbourhood) a brick that held a marker
-// before sweep t or before sweep t-1: markers move at most one cell per sweep
-// and every output depends only on markers within three cells, so outside the
-// band the state is constant and the result equals a full-grid sweep (the
-// second condition keeps both state buffers equal outside the band).
+// after sweep t-1, and the bricks that sweep t-1 found not quiet (it may have
+// changed them): markers move at most one cell per sweep and every output
+// depends only on markers within three cells, so outside the band the state
+// is constant and the result equals a full-grid sweep; the second set keeps
+// both state buffers equal outside the band.
 //
 // Lists.  Each sweep builds the band list of the next one: a brick holding a
 // marker claims its 27 neighbours (an atomic exchange of a per-brick stamp
@@ -117,7 +118,7 @@ long segcap_for(int n)
 
 // device work space carved out of the caller's scratch buffer
 struct Work {
-    uint32_t *cm[3];     // cm[t % 3][b] == t <=> brick b is in the band list of sweep t
+    uint32_t *cm;        // cm[b] == t <=> brick b is in the band list of sweep t (the last one it joined)
     uint32_t *fmark;     // fmark[b] == g <=> brick b is in the revisit list of Front2VOF generation g
     uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
     uint32_t *bchg;      // last sweep at which brick b was not quiet (see k_sweep)
@@ -144,7 +145,7 @@ size_t work_layout(int n, Work *w, char *base)
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return base ? base + o : nullptr; };
     char *p;
-    for (int k = 0; k < 3; ++k) { p = take(nb * 4); if (w) w->cm[k] = (uint32_t *)p; }
+    p = take(nb * 4); if (w) w->cm = (uint32_t *)p;
     p = take(nb * 4); if (w) w->fmark = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bcnt = (uint32_t *)p;
     p = take(nb * 4); if (w) w->bchg = (uint32_t *)p;
@@ -200,9 +201,9 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 }
 
 // Claims of list membership, batched per wave.  Two lists at once: the
-// bricks of the 3x3x3 neighbourhoods of `na` source bricks join list A
-// (membership markA[b] == vA) and the bricks at offsets (0 or -1 on each axis)
-// of `nbr` source bricks join list B.  An atomic exchange of the mark decides
+// bricks of the 3x3x3 neighbourhoods of `na` source bricks and the `ns`
+// bricks of srcS themselves join list A (membership markA[b] == vA), and the
+// bricks at offsets (0 or -1 on each axis) of `nbr` source bricks join list B.  An atomic exchange of the mark decides
 // the one claimant of each brick, which appends it, wave-aggregated, to
 // sub-list `sub` of its list.  Up to four claims per lane are in flight.
 struct ClaimList {
@@ -225,11 +226,12 @@ __device__ __forceinline__ void list_put(const ClaimList &L, uint32_t q, uint32_
     if (o < ocap) L.list[(size_t)kSub * scap + o] = b;
 }
 
-__device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const uint32_t *srcB, int nbr, int nb1,
-                                          ClaimList A, ClaimList B, int sub, uint32_t scap, uint32_t ocap)
+__device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const uint32_t *srcS, int ns,
+                                          const uint32_t *srcB, int nbr, int nb1, ClaimList A, ClaimList B, int sub,
+                                          uint32_t scap, uint32_t ocap)
 {
     const int lane = threadIdx.x & 63;
-    const int ta = na * 27, total = ta + nbr * 8;
+    const int ta = na * 27 + ns, total = ta + nbr * 8;
     for (int base = 0; base < total; base += 256) {
         uint32_t nbk[4];
         bool take[4], inA[4];
@@ -239,10 +241,12 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const ui
             take[u] = false;
             inA[u] = c < ta;
             nbk[u] = 0;
-            if (c < ta) {
+            if (c < na * 27) {
                 const uint32_t b = srcA[c / 27];
                 const int d = c % 27;
                 nbk[u] = brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1);
+            } else if (c < ta) {
+                nbk[u] = srcS[c - na * 27];
             } else if (c < total) {
                 const uint32_t b = srcB[(c - ta) >> 3];
                 const int d = (c - ta) & 7;
@@ -409,9 +413,9 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         long q = x + (long)g.n * y + g.nn * z;
         const bool hasm = __ballot((fl[q] & 0x70) != 0) != 0;
         if (hasm) {
-            const ClaimList A{w.cm[2], 2u, w.blist[2], w.bnum + 2 * kNum * kPad};
+            const ClaimList A{w.cm, 2u, w.blist[2], w.bnum + 2 * kNum * kPad};
             const uint32_t bp = bpack(bx, by, bz);
-            claim_two(&bp, 1, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap, (uint32_t)g.nb);
+            claim_two(&bp, 1, nullptr, 0, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap, (uint32_t)g.nb);
         }
     }
 }
@@ -421,9 +425,7 @@ __global__ void k_zero_work(Work w, Geo g)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < g.nb) {
-        w.cm[0][i] = 0;
-        w.cm[1][i] = 0;
-        w.cm[2][i] = 0;
+        w.cm[i] = 0;
         w.fmark[i] = 0;
         w.bcnt[i] = 0;
         w.bchg[i] = 0;
@@ -512,8 +514,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
     __syncthreads();
 }
 
-// One sweep: wave w takes the items w, w + nw, ... of the band lists of this
-// sweep and the previous one (a brick in both is taken once).  Per brick, one
+// One sweep: wave w takes the items w, w + nw, ... of the sweep's band list.  Per brick, one
 // lane per node: new node colours (one flip per aligned marker crossing a
 // node, Fig. 4), the aligned markers (land on the edge they reach, pairs
 // annihilate, Fig. 5a), which edges carry a marker afterwards (one marker iff
@@ -530,13 +531,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint32_t tq[kTaskCap];
     __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
-    __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap];
+    __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap], sbr[kClaimCap];
     __shared__ uint32_t ipre[2 * kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const uint32_t t = a.t;
-    const uint32_t *cm_cur = a.w.cm[t % 3];
-    uint32_t *cm_next = a.w.cm[(t + 1) % 3];
+    uint32_t *cm_next = a.w.cm;
     const int sub = wv % kSub;
     uint32_t *lnext = a.w.blist[(t + 1) % 4], *nnext = a.w.bnum + ((t + 1) % 4) * kNum * kPad;
     uint32_t *lrev = a.w.flist[a.fgen % 3], *nrev = a.w.fnum + (a.fgen % 3) * kNum * kPad;
@@ -574,18 +574,19 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
         it.total = (uint32_t)nb;
         it.nfirst = (uint32_t)nb;
     } else {
-        it.init(ipre, a.w.bnum + (t % 4) * kNum * kPad, a.w.bnum + ((t + 3) % 4) * kNum * kPad, a.w.blist[t % 4],
-                a.w.blist[(t + 3) % 4], (uint32_t)a.g.scap, (uint32_t)nb);
+        it.init(ipre, a.w.bnum + (t % 4) * kNum * kPad, nullptr, a.w.blist[t % 4], nullptr, (uint32_t)a.g.scap,
+                (uint32_t)nb);
     }
-    int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0;
+    int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0, ns = 0;
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
     auto claims = [&]() {
         __syncthreads();
-        claim_two(mbr, nm, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
+        claim_two(mbr, nm, sbr, ns, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
                   ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)a.g.scap, (uint32_t)nb);
         __syncthreads();
         nm = 0;
         nc = 0;
+        ns = 0;
     };
     // this wave's items item_of(wv, i), resolved one per lane (a static
     // schedule: a shared counter handing out items cost more than the
@@ -599,7 +600,6 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             int bb = a.full ? (have ? (int)bpack_lin((int)k, nb1) : -1) : it.brick_lane(have ? k : 0);
             if (!have || bb < 0 || bx_of((uint32_t)bb) >= nb1 || by_of((uint32_t)bb) >= nb1 || bz_of((uint32_t)bb) >= nb1)
                 bb = -1;
-            if (bb >= 0 && !a.full && k >= it.nfirst && cm_cur[blin((uint32_t)bb, nb1)] == t) bb = -1;   // also in this sweep's own list
             bl = bb;
         }
         unsigned long long pend = __ballot(bl >= 0);
@@ -620,7 +620,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                     ++nbat;
                 }
             }
-            if (nm + kBatch > kClaimCap || nc + kBatch > kClaimCap) claims();
+            if (nm + kBatch > kClaimCap || nc + kBatch > kClaimCap || ns + kBatch > kClaimCap) claims();
             int cfl = 0;
             uint8_t fr[kBatch][kR], fown[kBatch];
             uint32_t lastchg[kBatch];
@@ -834,11 +834,16 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // edges stored at its upper neighbours)
             const bool hasm = __ballot((out & 0x70) != 0) != 0;
             const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
+            // a brick that is not quiet joins the next sweep's list itself
+            // (through its markers' neighbourhood when it holds markers)
+            const bool self = !hasm && !quietj;
             if (lane == 0) {
                 if (hasm) mbr[nm] = (uint32_t)b;
+                if (self) sbr[ns] = (uint32_t)b;
                 if (hasm || chg) cbr[nc] = (uint32_t)b;
             }
             nm += hasm ? 1 : 0;
+            ns += self ? 1 : 0;
             nc += (hasm || chg) ? 1 : 0;
             fbc += fb;
             mergedc += merged;
