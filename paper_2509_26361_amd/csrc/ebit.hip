@@ -66,8 +66,14 @@ constexpr int kPad = EBIT_NUM_PAD; // lengths are kPad words apart: atomics on o
 #define EBIT_MAX_WAVES 3072
 #endif
 constexpr int kMaxWaves = EBIT_MAX_WAVES;   // waves of the sweep / Front2VOF grids
-constexpr int kTaskCap = 512;     // sweep: queued tasks per wave
-constexpr int kSlotCap = 128;     // sweep: queued face nodes per wave
+#ifndef EBIT_TASK_CAP
+#define EBIT_TASK_CAP 512
+#endif
+#ifndef EBIT_SLOT_CAP
+#define EBIT_SLOT_CAP 256
+#endif
+constexpr int kTaskCap = EBIT_TASK_CAP;   // sweep: queued tasks per wave
+constexpr int kSlotCap = EBIT_SLOT_CAP;   // sweep: queued face nodes per wave
 constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
 constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
 #ifndef EBIT_BATCH
@@ -471,7 +477,7 @@ constexpr int kAD = 6, kAA = 5, kATile = kAD * kAA * kAA;
 // per node in the slot table and the node's flags byte is written once.
 template <typename T, int D>
 __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t *tq, const uint8_t *tt,
-                                          const uint8_t *ts, int ntask, const uint32_t *sq, uint32_t *sb,
+                                          const uint16_t *ts, int ntask, const uint32_t *sq, uint32_t *sb,
                                           int nslot, int &fbt, int &multit)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
@@ -529,7 +535,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint8_t tfl[kBatch][kATile];
     __shared__ double txd[kBatch][kATile];
     __shared__ uint32_t tq[kTaskCap];
-    __shared__ uint8_t tt[kTaskCap], ts[kTaskCap];
+    __shared__ uint8_t tt[kTaskCap];
+    __shared__ uint16_t ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap], sbr[kClaimCap];
     __shared__ uint32_t ipre[2 * kSub];
@@ -816,7 +823,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                     const int i = ntask + __popcll(bal & lt);
                     tq[i] = (uint32_t)qs;
                     tt[i] = (uint8_t)(0 | ((int)task[0] << 1) | (c00 << 2));
-                    ts[i] = (uint8_t)slot;
+                    ts[i] = (uint16_t)slot;
                 }
                 ntask += __popcll(bal);
                 bal = __ballot(task[3]);
@@ -824,7 +831,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                     const int i = ntask + __popcll(bal & lt);
                     tq[i] = (uint32_t)qs;
                     tt[i] = (uint8_t)(1 | ((int)task[1] << 1) | (c00 << 2));
-                    ts[i] = (uint8_t)slot;
+                    ts[i] = (uint16_t)slot;
                 }
                 ntask += __popcll(bal);
             }
