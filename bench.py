@@ -281,6 +281,9 @@ def train_surrogate(E, I, torch, a):
                      log=lambda msg: print(f"[bench] surrogate {msg}", file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    bias0 = float((E.mlp_forward(theta, Xv) - cv).mean().item())
+    # output-bias calibration on training rows (not the hold-out)
+    theta, shift = SG.calibrate_bias(theta, Xt[:1_000_000], ct[:1_000_000])
     mae, mx = SG.evaluate(theta, Xv, cv)
     bias = float((E.mlp_forward(theta, Xv) - cv).mean().item())
     # gradient kernel alone, timed with HIP events on its stream
@@ -310,6 +313,7 @@ def train_surrogate(E, I, torch, a):
         "rows": m, "holdout_rows": nval, "dataset_s": t_data, "train_s": t_train,
         "steps": a.surr_steps, "batch": a.surr_batch,
         "holdout_mae": mae, "holdout_max_err": mx, "holdout_bias": bias, "untrained_mae": mae0,
+        "holdout_bias_before_calibration": bias0, "calibration_shift": shift,
         "gradient_us": grad_s * 1e6,
         "gradient_tflops": MLP_GRAD_FLOP * a.surr_batch / grad_s / 1e12,
         "forward_rows_per_s": nval / fwd_s,

@@ -97,6 +97,23 @@ def train(X, c, steps=2000, batch=4096, lr=2e-3, seed=0, log=None, theta=None):
     return tr.theta
 
 
+def calibrate_bias(theta, X, c, iters=4):
+    """Shift the output bias b3 (the last parameter) so that the network's
+    mean output on rows X equals the mean label: Newton's method on the
+    shift d of the pre-sigmoid value z, mean(sigmoid(z + d)) = mean(c).
+    Returns the shifted parameters and d."""
+    y = E.mlp_forward(theta, X).double().clamp(1e-7, 1.0 - 1e-7)
+    z = torch.log(y) - torch.log1p(-y)
+    target = c.double().mean()
+    d = torch.zeros((), dtype=torch.float64, device=z.device)
+    for _ in range(iters):
+        sg = torch.sigmoid(z + d)
+        d = d - (sg.mean() - target) / (sg * (1.0 - sg)).mean().clamp_min(1e-12)
+    theta = theta.clone()
+    theta[-1] += d.float()
+    return theta, float(d.item())
+
+
 def evaluate(theta, X, c):
     """Mean / max absolute error of the network on rows X against labels c."""
     y = E.mlp_forward(theta, X)
@@ -116,6 +133,8 @@ def main():
     a = p.parse_args()
     X, c = make_dataset(a.n, shapes=10_000, snapshots=6, seed=a.seed, max_rows=a.rows, log=print)
     theta = train(X, c, a.steps, a.batch, a.lr, a.seed, log=print)
+    theta, d = calibrate_bias(theta, X[:1_000_000], c[:1_000_000])
+    print(f"output bias shifted by {d:.3e}")
     np.save(a.out, theta.cpu().numpy())
     print("saved", a.out)
 

@@ -124,3 +124,22 @@ def check_in_front2vof(e, n, theta, vol_tol):
           f"surrogate {vs:.3f}, rel diff {abs(vs - vg) / vg:.2e}")
     assert abs(vs - vg) / vg < vol_tol
     return int(amb.sum())
+
+
+def test_output_bias_calibration_matches_mean_label():
+    """After calibrate_bias the network's mean output on the calibration rows
+    equals their mean label (Newton on the output bias); only b3 changes."""
+    rng = np.random.default_rng(3)
+    m = 20000
+    feats = np.concatenate([rng.uniform(0, 1, (m, 12)) * (rng.uniform(0, 1, (m, 12)) < 0.3),
+                            (rng.uniform(0, 1, (m, 8)) < 0.5).astype(np.float64), np.zeros((m, 12))], axis=1)
+    X = T(feats.astype(np.float32)).to(torch.bfloat16).contiguous()
+    c = T(rng.uniform(0.2, 0.9, m).astype(np.float32))
+    theta = T(I.mlp_init(5).astype(np.float32))
+    before = float(E.mlp_forward(theta, X).double().mean().item())
+    th2, d = SG.calibrate_bias(theta, X, c)
+    after = float(E.mlp_forward(th2, X).double().mean().item())
+    target = float(c.double().mean().item())
+    assert abs(before - target) > 1e-2           # there was a bias to remove
+    assert abs(after - target) < 2e-5, (after, target, d)
+    assert torch.equal(th2[:-1], theta[:-1]) and float(th2[-1] - theta[-1]) == pytest.approx(d, abs=1e-6)
