@@ -165,8 +165,12 @@ enum {
     EBIT_OPT_FULL_GRID = 1,   /* 1: process every cell, not only the band */
     EBIT_OPT_TIMING = 2,      /* k > 0: bracket every k-th launch of each kind (sweep, Front2VOF,
                                  Front2VOF with an x sweep) with HIP events on its stream; 0: off */
-    EBIT_OPT_FUSE = 3         /* 1 (default): ebit_advance fuses a Front2VOF with the next x sweep;
+    EBIT_OPT_FUSE = 3,        /* 1 (default): ebit_advance fuses a Front2VOF with the next x sweep;
                                  0: separate launches */
+    EBIT_OPT_SUBLIST_CAP = 4  /* k > 0: at most k entries per sub-list of the brick lists, the rest in
+                                 their overflow sub-list (for tests of that path); 0: the default.
+                                 Only before the first sweep or Front2VOF (else EBIT_ESTATE); rebuilds
+                                 the lists and synchronises the device. */
 };
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
 

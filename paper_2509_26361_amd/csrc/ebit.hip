@@ -1772,6 +1772,15 @@ int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, 
     return check_launch();
 }
 
+// work space cleared, band list of the first sweep built from the state
+int init_lists(ebit_ctx *c, hipStream_t st)
+{
+    const int nz = c->g.nb > c->g.nw ? c->g.nb : (c->g.nw > 4 * kNum ? c->g.nw : 4 * kNum);
+    hipLaunchKernelGGL(k_zero_work, dim3((nz + 255) / 256), dim3(256), 0, st, c->w, c->g);
+    hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, kMaxWaves)), dim3(64), 0, st, c->g, c->flags[0], c->w);
+    return check_launch();
+}
+
 template <typename T>
 int dataset_impl(ebit_ctx *c, void *x_bf16, float *cout, int64_t cap, int64_t *count, hipStream_t st)
 {
@@ -1897,10 +1906,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
         free(c);
         return EBIT_EHIP;
     }
-    const int nz = c->g.nb > c->g.nw ? c->g.nb : (c->g.nw > 4 * kNum ? c->g.nw : 4 * kNum);
-    hipLaunchKernelGGL(k_zero_work, dim3((nz + 255) / 256), dim3(256), 0, st, c->w, c->g);
-    hipLaunchKernelGGL(k_init_band, dim3(clampi(c->g.nb, kMaxWaves)), dim3(64), 0, st, c->g, c->flags[0], c->w);
-    int rc = check_launch();
+    int rc = init_lists(c, st);
     if (rc != EBIT_OK) {
         free(c);
         return rc;
@@ -2014,6 +2020,16 @@ int ebit_set_option(ebit_ctx *c, int option, int value)
     if (option == EBIT_OPT_FUSE) {
         c->fuse = value != 0;
         return EBIT_OK;
+    }
+    if (option == EBIT_OPT_SUBLIST_CAP) {
+        if (value < 0) return EBIT_EINVAL;
+        if (c->t != 2 || c->fgen != 1) return EBIT_ESTATE;   // the lists are rebuilt: only before any work
+        const int full = scap_for(c->n);
+        if (hipDeviceSynchronize() != hipSuccess) return EBIT_EHIP;
+        c->g.scap = value > 0 && value < full ? value : full;
+        const int rc = init_lists(c, nullptr);
+        if (rc != EBIT_OK) return rc;
+        return hipDeviceSynchronize() == hipSuccess ? EBIT_OK : EBIT_EHIP;
     }
     return EBIT_EINVAL;
 }

@@ -307,3 +307,36 @@ def test_timing_samples_every_kth_launch():
     e.set_option(E.EBIT_OPT_TIMING, 0)
     e.advance(U, [1.0] * 2, 0.5 / n, C)
     assert e.timing()["sweeps"] == 0
+
+
+@pytest.mark.parametrize("cap", [1, 3])
+def test_sublist_overflow_path_gives_same_results(cap):
+    """With the brick lists' sub-lists capped at `cap` entries nearly every
+    brick goes through the overflow sub-lists; the run must be bit-identical
+    to the default one.  The option is refused once work has started."""
+    n = 32
+    sh = I.sphere_shape(n, centre=(0.45, 0.5, 0.55), R=0.2)
+    U = [T(u) for u in I.deformation_velocity(n)]
+    dt = 0.5 / n
+    gs = [I.deformation_time_factor(k * dt, 3.0) for k in range(16)]
+    runs = []
+    for capped in (False, True):
+        e = E.Ebit(n, "fp64", dev())
+        e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+        if capped:
+            e.set_option(E.EBIT_OPT_SUBLIST_CAP, cap)
+        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        e.advance(U, gs, dt, C)
+        if capped:
+            with pytest.raises(E.EbitError):
+                e.set_option(E.EBIT_OPT_SUBLIST_CAP, 0)
+        torch.cuda.synchronize()
+        fl, s = e.state()
+        runs.append((fl.cpu().numpy(), [x.cpu().numpy() for x in s], C.cpu().numpy(), e.stats(C)))
+    (f0, s0, c0, st0), (f1, s1, c1, st1) = runs
+    assert np.array_equal(f0, f1)
+    for k in range(3):
+        assert np.array_equal(s0[k], s1[k])
+    assert np.array_equal(c0, c1)
+    assert st0["n_interfacial_sum"] == st1["n_interfacial_sum"]
+    assert st0["n_active_cells"] == st1["n_active_cells"]
