@@ -76,6 +76,9 @@ constexpr int kTaskCap = EBIT_TASK_CAP;   // sweep: queued tasks per wave
 constexpr int kSlotCap = EBIT_SLOT_CAP;   // sweep: queued face nodes per wave
 constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
 constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
+#ifndef EBIT_SURR_BLOCKS
+#define EBIT_SURR_BLOCKS 256   // one block (weights in 85 KB of LDS) per CU, each looping over segments
+#endif
 #ifndef EBIT_BATCH
 #define EBIT_BATCH 2
 #endif
@@ -1746,7 +1749,7 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     time_begin(c, st, 1);
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
-        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + 3) / 4, 256 * 2)), dim3(256), 0, st, a, c->surr);
+        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + 3) / 4, EBIT_SURR_BLOCKS)), dim3(256), 0, st, a, c->surr);
     time_end(c, st, 1);
     c->fgen++;
     c->last_t_f2v = c->t;
