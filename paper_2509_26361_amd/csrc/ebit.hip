@@ -21,7 +21,9 @@
 // builds the list of bricks that the next Front2VOF must revisit.
 //
 // Waves.  Both kernels run one 64-lane wave per workgroup over a fixed grid
-// of nw waves; wave w takes list items w, w + nw, ... (balanced to one brick).
+// of nw waves; a fixed map deals the list items to the waves (balanced to one
+// brick), runs of 16 consecutive items -- bricks appended together, hence
+// neighbours -- to the waves of one XCD.
 // A sweep wave stages each brick and a halo in LDS (one lane per node), writes
 // the new colours, aligned markers and uniform face colours, and queues the
 // work that needs the neighbourhood (new unaligned markers, colours of faces
@@ -308,32 +310,24 @@ __device__ __forceinline__ uint32_t item_of(uint32_t w, uint32_t i, uint32_t nw)
     return ((idx / kXcdChunk) * 8u + x) * kXcdChunk + idx % kXcdChunk;
 }
 
-// Items of a grid: the concatenation of up to two lists, each its kSub
-// sub-lists and then its overflow sub-list.  The inclusive prefixes of the
-// sub-list lengths of both lists are kept in LDS (pre[0..kSub) and
-// pre[kSub..2 kSub)).
+// Items of a grid: the entries of a list, its kSub sub-lists and then its
+// overflow sub-list.  The inclusive prefix sums of the sub-list lengths are
+// kept in LDS (pre[0..kSub)).
 struct Items {
-    uint32_t s0, s1;        // items in the sub-lists of list 0 / of list 1
-    uint32_t total, nfirst; // all items; items of list 0
-    const uint32_t *l0, *l1;
+    uint32_t s0;            // items in the sub-lists
+    uint32_t total;         // all items
+    const uint32_t *l0;
     const uint32_t *pre;
     uint32_t scap;
-    __device__ __forceinline__ void init(uint32_t *lds, const uint32_t *num0, const uint32_t *num1,
-                                         const uint32_t *list0, const uint32_t *list1, uint32_t scap_, uint32_t ocap)
+    __device__ __forceinline__ void init(uint32_t *lds, const uint32_t *num0, const uint32_t *list0, uint32_t scap_,
+                                         uint32_t ocap)
     {
         const int lane = threadIdx.x & 63;
         const uint32_t inc0 = wave_incl_scan(lane < kSub ? min(num0[lane * kPad], scap_) : 0u);
-        const uint32_t inc1 = num1 ? wave_incl_scan(lane < kSub ? min(num1[lane * kPad], scap_) : 0u) : 0u;
-        if (lane < kSub) {
-            lds[lane] = inc0;
-            lds[kSub + lane] = inc1;
-        }
+        if (lane < kSub) lds[lane] = inc0;
         s0 = __shfl(inc0, kSub - 1);
-        nfirst = s0 + min(num0[kSub * kPad], ocap);
-        s1 = num1 ? __shfl(inc1, kSub - 1) : 0u;
-        total = num1 ? nfirst + s1 + min(num1[kSub * kPad], ocap) : nfirst;
+        total = s0 + min(num0[kSub * kPad], ocap);
         l0 = list0;
-        l1 = list1;
         pre = lds;
         scap = scap_;
         __syncthreads();
@@ -341,19 +335,14 @@ struct Items {
     // brick of item k < total, a different k per lane
     __device__ __forceinline__ int brick_lane(uint32_t k) const
     {
-        const bool second = k >= nfirst;
-        const uint32_t kk = second ? k - nfirst : k;
-        const uint32_t ns = second ? s1 : s0;
-        const uint32_t *l = second ? l1 : l0;
-        if (kk >= ns) return (int)l[(size_t)kSub * scap + (kk - ns)];   // overflow sub-list
-        // j = the sub-lists that end at or before kk (binary search)
-        const uint32_t *p = pre + (second ? kSub : 0);
+        if (k >= s0) return (int)l0[(size_t)kSub * scap + (k - s0)];   // overflow sub-list
+        // j = the sub-lists that end at or before k (binary search)
         int j = 0;
 #pragma unroll
         for (int st = kSub / 2; st >= 1; st >>= 1)
-            if (p[j + st - 1] <= kk) j += st;
-        const uint32_t excl = j > 0 ? p[j - 1] : 0u;
-        return (int)l[(size_t)j * scap + (kk - excl)];
+            if (pre[j + st - 1] <= k) j += st;
+        const uint32_t excl = j > 0 ? pre[j - 1] : 0u;
+        return (int)l0[(size_t)j * scap + (k - excl)];
     }
 };
 
@@ -542,7 +531,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint16_t ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap], sbr[kClaimCap];
-    __shared__ uint32_t ipre[2 * kSub];
+    __shared__ uint32_t ipre[kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const uint32_t t = a.t;
@@ -582,10 +571,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     Items it;
     if (a.full) {
         it.total = (uint32_t)nb;
-        it.nfirst = (uint32_t)nb;
     } else {
-        it.init(ipre, a.w.bnum + (t % 4) * kNum * kPad, nullptr, a.w.blist[t % 4], nullptr, (uint32_t)a.g.scap,
-                (uint32_t)nb);
+        it.init(ipre, a.w.bnum + (t % 4) * kNum * kPad, a.w.blist[t % 4], (uint32_t)a.g.scap, (uint32_t)nb);
     }
     int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0, ns = 0;
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
@@ -1227,7 +1214,7 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
 {
     __shared__ uint32_t cq[kCellCap];
     __shared__ uint64_t cf[kCellCap];
-    __shared__ uint32_t ipre[2 * kSub];
+    __shared__ uint32_t ipre[kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
     const long nn = a.g.nn;
@@ -1240,8 +1227,7 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
     if (a.full) {
         it.total = (uint32_t)nb;
     } else {
-        it.init(ipre, a.w.fnum + (gen % 3) * kNum * kPad, nullptr, a.w.flist[gen % 3], nullptr, (uint32_t)a.g.scap,
-                (uint32_t)nb);
+        it.init(ipre, a.w.fnum + (gen % 3) * kNum * kPad, a.w.flist[gen % 3], (uint32_t)a.g.scap, (uint32_t)nb);
     }
     uint32_t *seg = a.w.ctask + (size_t)wv * a.g.segcap;
     long np = 0;
