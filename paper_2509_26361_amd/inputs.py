@@ -122,6 +122,52 @@ def sphere_shape(n, centre=(0.35, 0.35, 0.35), R=0.15) -> Shape:
     return Shape(n, phi, faces, _sphere_edge_roots(n, centre, R))
 
 
+def sphere_shape_device(n, centre=(0.35, 0.35, 0.35), R=0.15, device="cuda"):
+    """sphere_shape evaluated with torch in float64 on a device (the same
+    formulas, for grids too large to build on the host; equal to it up to an
+    ulp of the exact roots).  Returns (phi_nodes, [phi_faces x3],
+    [s_exact x3]) as (n,n,n) tensors."""
+    import torch
+    dt = torch.float64
+    h = 1.0 / n
+    ax = torch.arange(n, dtype=dt, device=device)
+
+    def phi_at(off):
+        comps = []
+        for a in range(3):
+            x = (ax + off[a]) * h - centre[a]
+            x = x - torch.round(x)
+            comps.append(x * x)
+        return R * R - (comps[2][:, None, None] + comps[1][None, :, None] + comps[0][None, None, :])
+
+    phi = phi_at((0.0, 0.0, 0.0))
+    faces = [phi_at((0.0, 0.5, 0.5)), phi_at((0.5, 0.0, 0.5)), phi_at((0.5, 0.5, 0.0))]
+    Rc = R * n
+    rel = []
+    for a in range(3):
+        x = ax - centre[a] * n
+        rel.append(x - n * torch.round(x / n))
+    roots = []
+    for e in range(3):
+        o = [b for b in range(3) if b != e]
+        rho2 = torch.zeros((n, n, n), dtype=dt, device=device)
+        for b in o:
+            shape = [1, 1, 1]
+            shape[2 - b] = n
+            rho2 = rho2 + (rel[b] * rel[b]).reshape(shape)
+        q = Rc * Rc - rho2
+        shape = [1, 1, 1]
+        shape[2 - e] = n
+        pe = rel[e].reshape(shape).expand(n, n, n)
+        root = torch.sqrt(torch.clamp(q, min=0.0))
+        inside = (pe * pe + rho2) < Rc * Rc
+        t = torch.where(inside, root - pe, -root - pe)
+        t = torch.where(q >= 0.0, t, torch.full_like(t, 0.5))
+        roots.append(torch.clamp(t, 0.0, 1.0))
+        del rho2, q, root, inside, t
+    return phi, faces, roots
+
+
 def spheres_shape(n, centres, radii, with_s=True) -> Shape:
     """Union of disjoint spheres: at each sample point the largest
     ``R^2 - |x-c|^2`` over the spheres, positive exactly inside the union.
