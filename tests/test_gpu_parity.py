@@ -120,7 +120,7 @@ def test_translation_run_parity_and_exact_shift():
             assert abs(s["volume"] - V0) < 1e-10
 
 
-@pytest.mark.parametrize("n,steps,every", [(32, 192, 16), (64, 96, 24)])
+@pytest.mark.parametrize("n,steps,every", [(32, 192, 16), (36, 108, 27), (64, 96, 24)])
 def test_deformation_run_parity(n, steps, every):
     """LeVeque deformation (sec. 3.2), CFL 0.5: state compared at intervals,
     bit-exact colours / existence, positions and C within 1e-12."""
