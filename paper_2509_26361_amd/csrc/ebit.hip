@@ -78,6 +78,10 @@ constexpr int kTaskCap = EBIT_TASK_CAP;   // sweep: queued tasks per wave
 constexpr int kSlotCap = EBIT_SLOT_CAP;   // sweep: queued face nodes per wave
 constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
 constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
+#ifndef EBIT_SURR_WAVES
+#define EBIT_SURR_WAVES 8
+#endif
+constexpr int kSurrWaves = EBIT_SURR_WAVES;   // waves per block of the surrogate pass (sharing the weights)
 #ifndef EBIT_SURR_BLOCKS
 #define EBIT_SURR_BLOCKS 256   // one block (weights in 85 KB of LDS) per CU, each looping over segments
 #endif
@@ -1405,21 +1409,22 @@ __device__ __forceinline__ void put_features(__bf16 *row, const uint8_t f[8], co
 // Front2VOF phase B with the learned surrogate: unambiguous interfacial cells
 // take the network's volume fraction, computed on matrix cores 16 cells at a
 // time; ambiguous ones fall back to the geometric construction.  One wave per
-// interfacial-cell segment; the block's four waves share the weights in LDS.
+// interfacial-cell segment; the block's eight waves share the weights in LDS
+// (124 KB per block: two waves per SIMD).
 template <typename T>
-__global__ __launch_bounds__(256) void k_f2v_b_surr(F2VArgs<T> a, const float *__restrict__ theta)
+__global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a, const float *__restrict__ theta)
 {
     using namespace ebit_mlp;
     __shared__ MlpWeights W;
-    __shared__ __bf16 xs[4][64 * kRow1];
-    __shared__ __bf16 h1s[4][16 * kRow2];
-    __shared__ uint32_t rows[4][64];
+    __shared__ __bf16 xs[kSurrWaves][64 * kRow1];
+    __shared__ __bf16 h1s[kSurrWaves][16 * kRow2];
+    __shared__ uint32_t rows[kSurrWaves][64];
     load_weights(W, theta);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
     const int nc = a.g.nw;
-    for (int ch = blockIdx.x * 4 + wave; ch < nc; ch += gridDim.x * 4) {
+    for (int ch = blockIdx.x * kSurrWaves + wave; ch < nc; ch += gridDim.x * kSurrWaves) {
         const uint32_t count = min(a.w.ccnt[ch], (uint32_t)a.g.segcap);
         int ambc = 0;
         for (uint32_t base = 0; base < count; base += 64) {
@@ -1735,7 +1740,8 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     time_begin(c, st, 1);
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
-        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + 3) / 4, EBIT_SURR_BLOCKS)), dim3(256), 0, st, a, c->surr);
+        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + kSurrWaves - 1) / kSurrWaves, EBIT_SURR_BLOCKS)),
+                           dim3(64 * kSurrWaves), 0, st, a, c->surr);
     time_end(c, st, 1);
     c->fgen++;
     c->last_t_f2v = c->t;
