@@ -314,6 +314,7 @@ def train_surrogate(E, I, torch, a):
         "steps": a.surr_steps, "batch": a.surr_batch,
         "holdout_mae": mae, "holdout_max_err": mx, "holdout_bias": bias, "untrained_mae": mae0,
         "holdout_bias_before_calibration": bias0, "calibration_shift": shift,
+        "train_us_per_step": t_train / a.surr_steps * 1e6,
         "gradient_us": grad_s * 1e6,
         "gradient_tflops": MLP_GRAD_FLOP * a.surr_batch / grad_s / 1e12,
         "forward_rows_per_s": nval / fwd_s,

@@ -207,7 +207,9 @@ int ebit_timing(ebit_ctx *ctx, ebit_timing_t *out);
 /* Number of parameters (19329). */
 int ebit_mlp_param_count(void);
 
-/* Device scratch bytes ebit_mlp_gradient needs. */
+/* Device scratch bytes ebit_mlp_gradient and ebit_mlp_train need (partial
+ * sums per workgroup and the parameters rounded to bfloat16 in the layout the
+ * kernels stage; about 20 MB).  The scratch pointer must be 16-byte aligned. */
 size_t ebit_mlp_scratch_bytes(void);
 
 /* y[i] = network(x row i) for m rows (device pointers).  Async on stream. */
@@ -224,8 +226,28 @@ int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, in
  * on theta with first / second moments m1, m2 (float32, param_count each). */
 int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t step, float lr, void *stream);
 
-/* Use the surrogate inside ebit_front2vof (theta: device parameters that stay
- * valid while set; NULL switches back to the geometric construction only).
+/* `steps` training steps on the device without returning to the caller: step
+ * s takes the mini-batch of rows idx[s batch .. (s + 1) batch - 1] of x / c
+ * (nrows rows each; idx NULL: rows 0 .. batch - 1 every step), the gradient
+ * of ebit_mlp_gradient on it, then the Adam step of ebit_mlp_adam with
+ * learning rate lr[s] and step count step0 + s + 1.  Same results, bit for
+ * bit, as those calls on the gathered rows.  idx: device int64, steps x batch
+ * entries in [0, nrows) (an entry outside that range is not read: its row
+ * counts as all-zero inputs with no loss, a wrong result, not a fault; the
+ * caller checks).  lr: host, `steps` floats.  losses: device, `steps` floats
+ * (the mean squared error of each step's batch before its update) or NULL.
+ * theta / m1 / m2 are updated in place; scratch as for ebit_mlp_gradient.
+ * Async on stream.  EBIT_EINVAL for null pointers, nrows <= 0, batch <= 0,
+ * steps < 0, step0 < 0, batch > nrows without idx, or unaligned scratch. */
+int ebit_mlp_train(float *theta, float *m1, float *m2, const void *x_bf16, const float *c, int64_t nrows,
+                   const int64_t *idx, int64_t batch, int64_t steps, const float *lr, int64_t step0, float *losses,
+                   void *scratch, size_t scratch_bytes, void *stream);
+
+/* Use the surrogate inside ebit_front2vof (theta: device parameters, read
+ * during this call: the weights are copied, rounded to bfloat16, into the
+ * context's work area, so later changes to theta need another call; the call
+ * synchronizes the device.  NULL switches back to the geometric construction
+ * only).
  * Cells with a 4-marker face or more than one loop always use the geometric
  * Front2VOF of sec. 2.5; the others take the network's output. */
 int ebit_set_surrogate(ebit_ctx *ctx, const float *theta);

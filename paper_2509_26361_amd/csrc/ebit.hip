@@ -148,6 +148,7 @@ struct Work {
     long long *doff;     // [nw] their offsets in the output
     unsigned long long *stat;   // ST_* totals
     double *part;        // 2 * kRedBlocks reduction partials
+    ebit_mlp::MlpImage *simg;   // the surrogate's weights in the layout its kernel stages in LDS
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -176,6 +177,7 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(nw * 8); if (w) w->doff = (long long *)p;
     p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
     p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
+    p = take(sizeof(ebit_mlp::MlpImage)); if (w) w->simg = (ebit_mlp::MlpImage *)p;
     return off;
 }
 
@@ -1412,14 +1414,14 @@ __device__ __forceinline__ void put_features(__bf16 *row, const uint8_t f[8], co
 // interfacial-cell segment; the block's eight waves share the weights in LDS
 // (124 KB per block: two waves per SIMD).
 template <typename T>
-__global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a, const float *__restrict__ theta)
+__global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a)
 {
     using namespace ebit_mlp;
     __shared__ MlpWeights W;
     __shared__ __bf16 xs[kSurrWaves][64 * kRow1];
     __shared__ __bf16 h1s[kSurrWaves][16 * kRow2];
     __shared__ uint32_t rows[kSurrWaves][64];
-    load_weights(W, theta);
+    copy_to_lds(&W, &a.w.simg->W, (int)sizeof(MlpWeights));
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
@@ -1473,6 +1475,16 @@ __global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a, co
         if (lane == 0) a.w.cs[CS_AMB * nc + ch] = (unsigned long long)sa;
     }
 }
+
+// the surrogate's weights image from its FP32 parameters
+__global__ __launch_bounds__(256) void k_surr_pack(const float *__restrict__ theta, ebit_mlp::MlpImage *__restrict__ img)
+{
+    using namespace ebit_mlp;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kNH * kRow1) pack_w1_slot(img, theta, t);
+    else if (t < kNH * kRow1 + kNParam - kOB1) image_store(img, kOB1 + (t - kNH * kRow1), theta[kOB1 + (t - kNH * kRow1)]);
+}
+constexpr int kSurrPackThreads = ebit_mlp::kNH * ebit_mlp::kRow1 + ebit_mlp::kNParam - ebit_mlp::kOB1;
 
 // Surrogate training rows: per segment, the unambiguous interfacial cells of
 // the last Front2VOF (count pass, then write pass at host-computed offsets).
@@ -1628,7 +1640,7 @@ struct ebit_ctx {
     uint32_t last_t_f2v;   // sweep counter at the last Front2VOF
     int full;              // process every brick
     const void *lastC;     // C array of the previous Front2VOF
-    const float *surr;     // surrogate parameters (NULL: geometric Front2VOF only)
+    int surr;              // the surrogate is set (weights image in w.simg); 0: geometric Front2VOF only
     int fuse;              // ebit_advance launches a Front2VOF with the next x sweep
     int timing;            // bracket every timing-th launch of each kind with events (0: off)
     unsigned tseen[3];     // launches of each kind since timing was switched on
@@ -1741,7 +1753,7 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
         hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + kSurrWaves - 1) / kSurrWaves, EBIT_SURR_BLOCKS)),
-                           dim3(64 * kSurrWaves), 0, st, a, c->surr);
+                           dim3(64 * kSurrWaves), 0, st, a);
     time_end(c, st, 1);
     c->fgen++;
     c->last_t_f2v = c->t;
@@ -1876,7 +1888,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->last_t_f2v = 0;
     c->full = 0;
     c->lastC = nullptr;
-    c->surr = nullptr;
+    c->surr = 0;
     c->fuse = 1;
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
@@ -1973,7 +1985,15 @@ int ebit_current(const ebit_ctx *c) { return c ? c->cur : -1; }
 int ebit_set_surrogate(ebit_ctx *c, const float *theta)
 {
     if (!c) return EBIT_EINVAL;
-    c->surr = theta;
+    if (!theta) {
+        c->surr = 0;
+        return EBIT_OK;
+    }
+    // theta may have been written on any stream; the image is complete before the call returns
+    if (hipDeviceSynchronize() != hipSuccess) return EBIT_EHIP;
+    hipLaunchKernelGGL(k_surr_pack, dim3((kSurrPackThreads + 255) / 256), dim3(256), 0, (hipStream_t)0, theta, c->w.simg);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize((hipStream_t)0) != hipSuccess) return EBIT_EHIP;
+    c->surr = 1;
     return EBIT_OK;
 }
 

@@ -58,8 +58,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ t
 constexpr int kPartial = kNParam + 1;     // gradient + loss sum
 
 struct GradShared {
-    MlpWeights W;
-    __bf16 w2r[kNH * kRow2];               // W2 as [k][j] for dz2 W2^T
+    MlpImage img;                          // weights; img.w2r: W2 as [k][j] for dz2 W2^T
     __bf16 xt[4][16 * kRow1];              // input tiles
     __bf16 h1[4][16 * kRow2];              // first hidden layer (bf16)
     __bf16 dz2[4][16 * kRow2];
@@ -76,16 +75,39 @@ __device__ __forceinline__ float col_sum(float v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ theta, const uint16_t *__restrict__ x,
-                                                  const float *__restrict__ c, long m, float *__restrict__ partial)
+// the parameters' image (see MlpImage), built by one launch
+__global__ __launch_bounds__(256) void k_mlp_pack(const float *__restrict__ theta, MlpImage *__restrict__ img)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kNH * kRow1) pack_w1_slot(img, theta, t);
+    else if (t < kNH * kRow1 + kNParam - kOB1) image_store(img, kOB1 + (t - kNH * kRow1), theta[kOB1 + (t - kNH * kRow1)]);
+}
+constexpr int kPackThreads = kNH * kRow1 + kNParam - kOB1;
+
+// A fragment of batch rows row0 .. row0 + 15: batch row r is data row
+// idx[r] (idx NULL: row r); rows past the batch or with an index outside
+// [0, nrows) read as zero
+__device__ __forceinline__ bf16x8 load_batch_x(const uint16_t *__restrict__ x, const int64_t *__restrict__ idx,
+                                               long nrows, long m, long row0)
+{
+    const int l = threadIdx.x & 63;
+    const long row = row0 + (l & 15);
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (row < m) {
+        const long src = idx ? idx[row] : row;
+        if (src >= 0 && src < nrows) v = *(const u16x8 *)(x + src * kKIn + 8 * (l >> 4));
+    }
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad(const MlpImage *__restrict__ img, const uint16_t *__restrict__ x,
+                                                  const float *__restrict__ c, const int64_t *__restrict__ idx,
+                                                  long nrows, long m, float *__restrict__ partial)
 {
     __shared__ GradShared S;
-    load_weights(S.W, theta);
-    for (int i = threadIdx.x; i < kNH * kNH; i += blockDim.x) {
-        int k = i / kNH, j = i % kNH;
-        S.w2r[k * kRow2 + j] = to_bf16(theta[kOW2 + k * kNH + j]);
-    }
+    copy_to_lds(&S.img, img, (int)sizeof(MlpImage));
     __syncthreads();
+    const MlpWeights &W = S.img.W;
     const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
@@ -108,17 +130,19 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ thet
         // forward, keeping z1 and z2 (accumulator layout) and h1 in LDS
         f32x4 z1[8], z2[8];
         float yv[4];
-        const bf16x8 ax = load_x(x, m, row0);
+        const bf16x8 ax = load_batch_x(x, idx, nrows, m, row0);
         *(bf16x8 *)&S.xt[wave][lr * kRow1 + 8 * lg] = ax;
-        forward_tile(S.W, S.h1[wave], ax, yv, z1, z2);
+        forward_tile(W, S.h1[wave], ax, yv, z1, z2);
         // dz3 for rows 4 lg + r (valid in lanes lr == 0, broadcast to the group)
         float dz3[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             long row = row0 + 4 * lg + r;
             float v = 0.f;
-            if (lr == 0 && row < m) {
-                float cy = c[row];
+            long src = -1;
+            if (lr == 0 && row < m) src = idx ? idx[row] : row;
+            if (src >= 0 && src < nrows) {
+                float cy = c[src];
                 float d = yv[r] - cy;
                 ploss += d * d;
                 v = inv_m * d * yv[r] * (1.f - yv[r]);
@@ -130,7 +154,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ thet
 #pragma unroll
         for (int jt = 0; jt < 8; ++jt) {
             const int j = 16 * jt + lr;
-            const float w3 = S.W.w3[j], b2 = S.W.b2[j];
+            const float w3 = W.w3[j], b2 = W.b2[j];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float zz = z2[jt][r] + b2;
@@ -151,14 +175,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ thet
             bf16x8 a = *(const bf16x8 *)&S.dz2[wave][lr * kRow2 + 32 * ks + 8 * lg];
 #pragma unroll
             for (int kt = 0; kt < 8; ++kt) {
-                bf16x8 b = *(const bf16x8 *)&S.w2r[(16 * kt + lr) * kRow2 + 32 * ks + 8 * lg];
+                bf16x8 b = *(const bf16x8 *)&S.img.w2r[(16 * kt + lr) * kRow2 + 32 * ks + 8 * lg];
                 dh[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, dh[kt], 0, 0, 0);
             }
         }
 #pragma unroll
         for (int kt = 0; kt < 8; ++kt) {
             const int k = 16 * kt + lr;
-            const float b1 = S.W.b1[k];
+            const float b1 = W.b1[k];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float d1 = (z1[kt][r] + b1) > 0.f ? dh[kt][r] : 0.f;
@@ -276,35 +300,109 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ thet
     }
 }
 
-// gradient and loss = sum of the block partials in block order (deterministic)
+// Sum of the block partials of entry p (kNParam: the loss sum), the same
+// fixed order at every call: wave w of the block adds blocks
+// [w q, (w + 1) q) in order (q = ceil(nblocks / 4)), then the four wave sums
+// are added in wave order.  Valid in the lanes of wave 0.
+__device__ __forceinline__ float reduce_partials(const float *__restrict__ partial, int nblocks, int p,
+                                                 float (*red)[64])
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = (nblocks + 3) / 4, b0 = wave * q, b1 = min(nblocks, b0 + q);
+    float s = 0.f;
+    if (p < kPartial) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(b + u) * kPartial + p];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; b < b1; ++b) s += partial[(size_t)b * kPartial + p];
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    return ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// gradient (and the loss, mean over the m rows) from the partials: 64
+// entries per workgroup
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ partial, int nblocks, long m,
                                                     float *__restrict__ grad, float *__restrict__ loss)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > kNParam) return;
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * kPartial + p];
+    __shared__ float red[4][64];
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+    const float s = reduce_partials(partial, nblocks, p, red);
+    if (threadIdx.x >= 64) return;
     if (p < kNParam) grad[p] = s;
-    else if (loss) *loss = s / (float)m;
+    else if (p == kNParam && loss) *loss = s / (float)m;
+}
+
+struct AdamStep {
+    float lr, bc1, bc2;   // learning rate, bias corrections 1 - beta^t
+};
+
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on parameter p
+__device__ __forceinline__ float adam_update(float *__restrict__ theta, float *__restrict__ m1,
+                                             float *__restrict__ m2, int p, float g, AdamStep a)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float u = b1 * m1[p] + (1.f - b1) * g;
+    float v = b2 * m2[p] + (1.f - b2) * g * g;
+    m1[p] = u;
+    m2[p] = v;
+    float mh = u / a.bc1, vh = v / a.bc2;
+    float t = theta[p] - a.lr * mh / (sqrtf(vh) + eps);
+    theta[p] = t;
+    return t;
 }
 
 __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ theta, float *__restrict__ m1,
-                                                  float *__restrict__ m2, const float *__restrict__ grad, float lr,
-                                                  float bc1, float bc2)
+                                                  float *__restrict__ m2, const float *__restrict__ grad, AdamStep a)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kNParam) return;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    float g = grad[p];
-    float a = b1 * m1[p] + (1.f - b1) * g;
-    float v = b2 * m2[p] + (1.f - b2) * g * g;
-    m1[p] = a;
-    m2[p] = v;
-    float mh = a / bc1, vh = v / bc2;
-    theta[p] -= lr * mh / (sqrtf(vh) + eps);
+    adam_update(theta, m1, m2, p, grad[p], a);
+}
+
+// one training step after k_mlp_grad: gradient from the partials, Adam, and
+// the new parameters into the image the next step's gradient reads
+__global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float *__restrict__ partial, int nblocks, long m,
+                                                         float *__restrict__ loss, float *__restrict__ theta,
+                                                         float *__restrict__ m1, float *__restrict__ m2,
+                                                         MlpImage *__restrict__ img, AdamStep a)
+{
+    __shared__ float red[4][64];
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+    const float s = reduce_partials(partial, nblocks, p, red);
+    if (threadIdx.x >= 64) return;
+    if (p < kNParam) image_store(img, p, adam_update(theta, m1, m2, p, s, a));
+    else if (p == kNParam && loss) *loss = s / (float)m;
 }
 
 constexpr int kGradBlocks = 256;
+constexpr size_t kPartialBytes = (size_t)kGradBlocks * kPartial * sizeof(float);   // a multiple of 16
+
+inline MlpImage *image_of(void *scratch) { return (MlpImage *)((char *)scratch + kPartialBytes); }
+
+inline int grad_blocks(long m)
+{
+    const long groups = (m + 63) / 64;
+    return groups < kGradBlocks ? (int)groups : kGradBlocks;
+}
+
+inline AdamStep adam_step(int64_t t, float lr)
+{
+    return AdamStep{lr, (float)(1.0 - pow(0.9, (double)t)), (float)(1.0 - pow(0.999, (double)t))};
+}
+
+// scratch: partial sums, then the parameters' image (16-byte aligned)
+inline int scratch_ok(const void *scratch, size_t bytes)
+{
+    if (!scratch || ((uintptr_t)scratch & 15)) return EBIT_EINVAL;
+    return bytes < kPartialBytes + sizeof(MlpImage) ? EBIT_ESCRATCH : EBIT_OK;
+}
 
 }  // namespace
 
@@ -312,7 +410,7 @@ extern "C" {
 
 int ebit_mlp_param_count(void) { return kNParam; }
 
-size_t ebit_mlp_scratch_bytes(void) { return (size_t)kGradBlocks * kPartial * sizeof(float); }
+size_t ebit_mlp_scratch_bytes(void) { return kPartialBytes + sizeof(MlpImage); }
 
 int ebit_mlp_forward(const float *theta, const void *x_bf16, int64_t m, float *y, void *stream)
 {
@@ -329,14 +427,15 @@ int ebit_mlp_forward(const float *theta, const void *x_bf16, int64_t m, float *y
 int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad, float *loss,
                       void *scratch, size_t scratch_bytes, void *stream)
 {
-    if (!theta || !x_bf16 || !c || !grad || !scratch || m <= 0) return EBIT_EINVAL;
-    if (scratch_bytes < ebit_mlp_scratch_bytes()) return EBIT_ESCRATCH;
-    long groups = (m + 63) / 64;
-    int blocks = groups < kGradBlocks ? (int)groups : kGradBlocks;
+    if (!theta || !x_bf16 || !c || !grad || m <= 0) return EBIT_EINVAL;
+    if (int e = scratch_ok(scratch, scratch_bytes)) return e;
+    const int blocks = grad_blocks(m);
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, theta, (const uint16_t *)x_bf16, c, (long)m,
-                       (float *)scratch);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, st, (const float *)scratch, blocks,
+    MlpImage *img = image_of(scratch);
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kPackThreads + 255) / 256), dim3(256), 0, st, theta, img);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, img, (const uint16_t *)x_bf16, c,
+                       (const int64_t *)nullptr, (long)m, (long)m, (float *)scratch);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)scratch, blocks,
                        (long)m, grad, loss);
     return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
 }
@@ -344,9 +443,33 @@ int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, in
 int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t step, float lr, void *stream)
 {
     if (!theta || !m1 || !m2 || !grad || step < 1) return EBIT_EINVAL;
-    float bc1 = (float)(1.0 - pow(0.9, (double)step)), bc2 = (float)(1.0 - pow(0.999, (double)step));
     hipLaunchKernelGGL(k_mlp_adam, dim3((kNParam + 255) / 256), dim3(256), 0, (hipStream_t)stream, theta, m1, m2, grad,
-                       lr, bc1, bc2);
+                       adam_step(step, lr));
+    return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
+}
+
+int ebit_mlp_train(float *theta, float *m1, float *m2, const void *x_bf16, const float *c, int64_t nrows,
+                   const int64_t *idx, int64_t batch, int64_t steps, const float *lr, int64_t step0, float *losses,
+                   void *scratch, size_t scratch_bytes, void *stream)
+{
+    if (!theta || !m1 || !m2 || !x_bf16 || !c || nrows <= 0 || batch <= 0 || steps < 0 || step0 < 0) return EBIT_EINVAL;
+    if (steps > 0 && !lr) return EBIT_EINVAL;
+    if (!idx && batch > nrows) return EBIT_EINVAL;
+    if (int e = scratch_ok(scratch, scratch_bytes)) return e;
+    if (steps == 0) return EBIT_OK;
+    const int blocks = grad_blocks(batch);
+    hipStream_t st = (hipStream_t)stream;
+    MlpImage *img = image_of(scratch);
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kPackThreads + 255) / 256), dim3(256), 0, st, theta, img);
+    for (int64_t s = 0; s < steps; ++s) {
+        hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, img, (const uint16_t *)x_bf16, c,
+                           idx ? idx + s * batch : (const int64_t *)nullptr, (long)nrows, (long)batch,
+                           (float *)scratch);
+        hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)scratch,
+                           blocks, (long)batch, losses ? losses + s : (float *)nullptr, theta, m1, m2, img,
+                           adam_step(step0 + s + 1, lr[s]));
+        if ((s & 255) == 255 && hipGetLastError() != hipSuccess) return EBIT_EHIP;
+    }
     return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
 }
 

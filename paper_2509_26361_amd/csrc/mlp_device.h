@@ -33,12 +33,58 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // weights staged in LDS in the layout of the B operands of the forward pass
-struct MlpWeights {
+struct alignas(16) MlpWeights {
     __bf16 w1[kNH * kRow1];    // [j][k] = W1[k][j], k < 20; zero for 20 <= k < 32
     __bf16 w2[kNH * kRow2];    // [j][k] = W2[k][j]
     float b1[kNH], b2[kNH], w3[kNH];
     float b3;
 };
+
+// the bfloat16 weights of the forward pass and W2 once more as [k][j] (the B
+// operand of dz2 W2^T in the backward pass): built in device memory from the
+// FP32 parameters, then copied whole into LDS by every workgroup
+struct alignas(16) MlpImage {
+    MlpWeights W;
+    __bf16 w2r[kNH * kRow2];
+};
+
+// the image entries of parameter p (value v); W1 columns 20..31 are zero and
+// are written by pack_w1_slot, the other pad entries are never read
+__device__ __forceinline__ void image_store(MlpImage *img, int p, float v)
+{
+    if (p < kOB1) {
+        const int k = p / kNH, j = p % kNH;
+        img->W.w1[j * kRow1 + k] = to_bf16(v);
+    } else if (p < kOW2) {
+        img->W.b1[p - kOB1] = v;
+    } else if (p < kOB2) {
+        const int q = p - kOW2, k = q / kNH, j = q % kNH;
+        const __bf16 b = to_bf16(v);
+        img->W.w2[j * kRow2 + k] = b;
+        img->w2r[k * kRow2 + j] = b;
+    } else if (p < kOW3) {
+        img->W.b2[p - kOB2] = v;
+    } else if (p < kOB3) {
+        img->W.w3[p - kOW3] = v;
+    } else {
+        img->W.b3 = v;
+    }
+}
+
+// slot t < kNH * kRow1 of the W1 image: W1[k][j] for k < 20, zero otherwise
+__device__ __forceinline__ void pack_w1_slot(MlpImage *img, const float *__restrict__ theta, int t)
+{
+    const int j = t / kRow1, k = t % kRow1;
+    img->W.w1[t] = k < kNIn ? to_bf16(theta[kOW1 + k * kNH + j]) : to_bf16(0.f);
+}
+
+// copy `bytes` (a multiple of 16) from device memory into LDS, whole block
+__device__ __forceinline__ void copy_to_lds(void *dst, const void *__restrict__ src, int bytes)
+{
+    const uint4 *s = (const uint4 *)src;
+    uint4 *d = (uint4 *)dst;
+    for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
 
 __device__ inline void load_weights(MlpWeights &W, const float *__restrict__ theta)
 {

@@ -103,6 +103,9 @@ def lib():
         L.ebit_mlp_gradient.restype = ctypes.c_int
         L.ebit_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float, P]
         L.ebit_mlp_adam.restype = ctypes.c_int
+        L.ebit_mlp_train.argtypes = [P, P, P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, P,
+                                     ctypes.c_int64, P, P, ctypes.c_size_t, P]
+        L.ebit_mlp_train.restype = ctypes.c_int
         L.ebit_set_surrogate.argtypes = [P, P]
         L.ebit_set_surrogate.restype = ctypes.c_int
         L.ebit_surrogate_dataset.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
@@ -327,3 +330,24 @@ class MlpTrainer:
         _check(lib().ebit_mlp_adam(_ptr(self.theta), _ptr(self.m1), _ptr(self.m2), _ptr(self.grad), self.t,
                                    float(lr), _stream(stream)), "ebit_mlp_adam")
         return self.loss
+
+    def train(self, x_bf16, c, idx, lrs, stream=None):
+        """len(lrs) steps in one native call; step s uses rows
+        idx[s * batch:(s + 1) * batch] (idx: int64 device tensor of
+        len(lrs) x batch entries in [0, rows)).  Returns the per-step losses
+        (device tensor)."""
+        steps = len(lrs)
+        nrows = x_bf16.shape[0]
+        if idx.dtype != torch.int64 or not idx.is_contiguous() or steps == 0 or idx.numel() % steps:
+            raise ValueError("idx must be a contiguous int64 tensor of steps x batch entries")
+        if int(idx.min()) < 0 or int(idx.max()) >= nrows:
+            raise ValueError("row index out of range")
+        batch = idx.numel() // steps
+        lr = (ctypes.c_float * steps)(*[float(v) for v in lrs])
+        lrp = ctypes.cast(lr, ctypes.c_void_p)
+        losses = torch.empty(steps, dtype=torch.float32, device=self.theta.device)
+        _check(lib().ebit_mlp_train(_ptr(self.theta), _ptr(self.m1), _ptr(self.m2), _ptr(x_bf16), _ptr(c), nrows,
+                                    _ptr(idx), batch, steps, lrp, self.t, _ptr(losses), _ptr(self.scratch),
+                                    self.scratch.numel(), _stream(stream)), "ebit_mlp_train")
+        self.t += steps
+        return losses

@@ -5,7 +5,8 @@ ellipsoids (semi-axes 2..40 cells, random orientation) are initialised and
 advected by the 3D deformation field on the GPU (FP64 path); at snapshots the
 geometric Front2VOF labels every unambiguous interfacial cell
 (ebit_surrogate_dataset).  Training runs entirely in the library's
-bfloat16-MFMA kernels (ebit_mlp_gradient, ebit_mlp_adam).
+bfloat16-MFMA kernels (ebit_mlp_train: gradient, Adam and the mini-batch
+gather on the device, many steps per call).
 
     python -m paper_2509_26361_amd.surrogate --rows 10000000 --out theta.npy
 """
@@ -47,9 +48,8 @@ def make_dataset(n=128, shapes=8, snapshots=4, seed=0, device="cuda", max_rows=N
         step = int(rng.integers(0, 3 * n))                 # random phase of the period
         for s in range(snapshots):
             adv = int(rng.integers(1, n))
-            for _ in range(adv):
-                e.step(Ud, I.deformation_time_factor(step * dt, 3.0), dt)
-                step += 1
+            e.advance(Ud, [I.deformation_time_factor((step + j) * dt, 3.0) for j in range(adv)], dt)
+            step += adv
             C = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
             e.front2vof(C)                                  # new C: every cell recomputed
             x, c = e.dataset()
@@ -72,28 +72,34 @@ def make_dataset(n=128, shapes=8, snapshots=4, seed=0, device="cuda", max_rows=N
 
 def train(X, c, steps=2000, batch=4096, lr=2e-3, seed=0, log=None, theta=None):
     """Adam on mini-batches drawn by a seeded permutation; cosine-decayed
-    learning rate.  Returns the float32 parameter vector (device)."""
+    learning rate.  The steps run on the device in chunks of a tenth of the
+    run (one native call each; the mini-batch gather happens inside the
+    gradient kernel).  Returns the float32 parameter vector (device)."""
     dev = X.device
     if theta is None:
         theta = torch.from_numpy(I.mlp_init(seed).astype(np.float32)).to(dev)
     tr = E.MlpTrainer(theta, dev)
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    g = torch.Generator(device=dev).manual_seed(seed)   # permutations drawn on the device
     m = X.shape[0]
-    perm = torch.randperm(m, generator=g).to(dev)
+    perm = torch.randperm(m, generator=g, device=dev)
     pos = 0
     t0 = time.perf_counter()
-    for k in range(steps):
-        if pos + batch > m:
-            perm = torch.randperm(m, generator=g).to(dev)
-            pos = 0
-        idx = perm[pos:pos + batch]
-        pos += batch
-        xb = X.index_select(0, idx)
-        cb = c.index_select(0, idx)
-        lrk = lr * 0.5 * (1.0 + math.cos(math.pi * k / steps))
-        loss = tr.step(xb, cb, lrk)
-        if log and (k % max(1, steps // 10) == 0 or k == steps - 1):
-            log(f"step {k}: loss {float(loss.item()):.3e} ({time.perf_counter() - t0:.1f} s)")
+    chunk = max(1, steps // 10)
+    for k0 in range(0, steps, chunk):
+        ks = range(k0, min(steps, k0 + chunk))
+        parts = []
+        for k in ks:
+            if pos + batch > m:
+                perm = torch.randperm(m, generator=g, device=dev)
+                pos = 0
+            parts.append(perm[pos:pos + batch])
+            pos += batch
+        lrs = [lr * 0.5 * (1.0 + math.cos(math.pi * k / steps)) for k in ks]
+        losses = tr.train(X, c, torch.cat(parts), lrs)
+        if log:
+            log(f"step {k0}: loss {float(losses[0].item()):.3e} ({time.perf_counter() - t0:.1f} s)")
+            if ks[-1] == steps - 1:
+                log(f"step {steps - 1}: loss {float(losses[-1].item()):.3e} ({time.perf_counter() - t0:.1f} s)")
     return tr.theta
 
 

@@ -94,3 +94,47 @@ def test_adam_matches_oracle_and_training_reduces_loss():
     assert np.max(np.abs(got - want)) < 1e-6
     losses = [float(tr.step(xb, cg, 1e-3).item()) for _ in range(300)]
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
+
+
+def test_native_training_loop_equals_step_by_step():
+    """ebit_mlp_train (gather inside the gradient kernel, reduction fused with
+    Adam, weights image updated in place) against gradient + Adam calls on
+    rows gathered by torch: parameters, moments and losses bit for bit, over
+    steps with repeated rows and a ragged last gradient group."""
+    rng = np.random.default_rng(11)
+    _, tg = theta32(6)
+    m, batch, steps = 3000, 520, 7
+    X = to_bf16_rows(np.concatenate([rng.uniform(0, 1, size=(m, 12)), rng.integers(0, 2, size=(m, 8))], axis=1))
+    c = torch.from_numpy(rng.uniform(0, 1, m).astype(np.float32)).to(dev())
+    idx = torch.from_numpy(rng.integers(0, m, size=steps * batch)).to(dev())
+    lrs = [1e-3 * (1.0 + 0.1 * s) for s in range(steps)]
+    a = E.MlpTrainer(tg.clone(), dev())
+    b = E.MlpTrainer(tg.clone(), dev())
+    la = a.train(X, c, idx, lrs).cpu().numpy()
+    lb = []
+    for s in range(steps):
+        rows = idx[s * batch:(s + 1) * batch]
+        lb.append(float(b.step(X.index_select(0, rows), c.index_select(0, rows), lrs[s]).item()))
+    torch.cuda.synchronize()
+    assert a.t == b.t == steps
+    assert torch.equal(a.theta, b.theta)
+    assert torch.equal(a.m1, b.m1) and torch.equal(a.m2, b.m2)
+    assert np.array_equal(la, np.array(lb, dtype=np.float32))
+    # a second call continues from the same state (step count, image rebuilt)
+    la2 = a.train(X, c, idx[:2 * batch].contiguous(), lrs[:2]).cpu().numpy()
+    for s in range(2):
+        rows = idx[s * batch:(s + 1) * batch]
+        assert float(b.step(X.index_select(0, rows), c.index_select(0, rows), lrs[s]).item()) == la2[s]
+    assert torch.equal(a.theta, b.theta)
+
+
+def test_native_training_loop_rejects_bad_indices():
+    _, tg = theta32(7)
+    X = to_bf16_rows(np.zeros((100, 20)))
+    c = torch.zeros(100, dtype=torch.float32, device=dev())
+    tr = E.MlpTrainer(tg.clone(), dev())
+    for bad in (torch.tensor([0, 100], device=dev()), torch.tensor([-1, 3], device=dev()),
+                torch.tensor([0, 1, 2], device=dev())):
+        with pytest.raises(ValueError):
+            tr.train(X, c, bad, [1e-3, 1e-3])
+    assert torch.equal(tr.theta, tg)
