@@ -167,10 +167,14 @@ enum {
                                  Front2VOF with an x sweep) with HIP events on its stream; 0: off */
     EBIT_OPT_FUSE = 3,        /* 1 (default): ebit_advance fuses a Front2VOF with the next x sweep;
                                  0: separate launches */
-    EBIT_OPT_SUBLIST_CAP = 4  /* k > 0: at most k entries per sub-list of the brick lists, the rest in
+    EBIT_OPT_SUBLIST_CAP = 4, /* k > 0: at most k entries per sub-list of the brick lists, the rest in
                                  their overflow sub-list (for tests of that path); 0: the default.
                                  Only before the first sweep or Front2VOF (else EBIT_ESTATE); rebuilds
                                  the lists and synchronises the device. */
+    EBIT_OPT_ORDER = 5        /* 1: before each sweep and each Front2VOF that is not over the whole
+                                 grid, its brick list is rewritten in brick order (three small extra
+                                 launches each; fewer HBM fetches on large bands); 0: claim order.
+                                 Results are identical.  Default 1 for n >= 512, else 0. */
 };
 int ebit_set_option(ebit_ctx *ctx, int option, int value);
 

@@ -78,6 +78,9 @@ constexpr int kTaskCap = EBIT_TASK_CAP;   // sweep: queued tasks per wave
 constexpr int kSlotCap = EBIT_SLOT_CAP;   // sweep: queued face nodes per wave
 constexpr int kCellCap = 192;     // Front2VOF: queued interfacial cells per wave
 constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join the next lists
+#ifndef EBIT_ORDER_MIN_N
+#define EBIT_ORDER_MIN_N 512
+#endif
 #ifndef EBIT_SURR_WAVES
 #define EBIT_SURR_WAVES 8
 #endif
@@ -131,6 +134,8 @@ long segcap_for(int n)
     return ((nb + nw - 1) / nw + 2) * 64;
 }
 
+constexpr int kOrderBlocks = 1024;   // workgroups of the band-ordering pass
+
 // device work space carved out of the caller's scratch buffer
 struct Work {
     uint32_t *cm;        // cm[b] == t <=> brick b is in the band list of sweep t (the last one it joined)
@@ -149,6 +154,7 @@ struct Work {
     unsigned long long *stat;   // ST_* totals
     double *part;        // 2 * kRedBlocks reduction partials
     ebit_mlp::MlpImage *simg;   // the surrogate's weights in the layout its kernel stages in LDS
+    uint32_t *ocnt;      // [kOrderBlocks] band-ordering counts / offsets
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -178,6 +184,7 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
     p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
     p = take(sizeof(ebit_mlp::MlpImage)); if (w) w->simg = (ebit_mlp::MlpImage *)p;
+    p = take(kOrderBlocks * 4); if (w) w->ocnt = (uint32_t *)p;
     return off;
 }
 
@@ -421,6 +428,75 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
             const uint32_t bp = bpack(bx, by, bz);
             claim_two(&bp, 1, nullptr, 0, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap, (uint32_t)g.nb);
         }
+    }
+}
+
+// A brick list rewritten in brick order (bx fastest, then by, bz): the
+// bricks whose stamp equals `val` (the band list of sweep t: cm == t; the
+// revisit list of Front2VOF generation g: fmark == g), all in the overflow
+// sub-list, the kSub sub-lists emptied.  Consecutive items are then
+// neighbouring bricks, which the item schedule hands to one XCD in runs of
+// kXcdChunk, so the 128-byte lines a run's brick rows share (four bricks per
+// line of a fraction array) and its halos are fetched into that XCD's L2
+// once.  Three passes: counts per block of `per` bricks, their exclusive
+// scan, the writes.
+struct OrderArgs {
+    const uint32_t *stamp;
+    uint32_t val;
+    uint32_t *out;        // the list's overflow sub-list
+    uint32_t *num;        // the list's kNum lengths, kPad words apart
+    uint32_t *cnt;        // [kOrderBlocks]
+    uint32_t nb, per;
+    int nb1;
+};
+
+__global__ __launch_bounds__(256) void k_order_count(OrderArgs o)
+{
+    __shared__ uint32_t ws[4];
+    const uint32_t b0 = blockIdx.x * o.per, b1 = min(b0 + o.per, o.nb);
+    int c = 0;
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += 256) c += o.stamp[b] == o.val ? 1 : 0;
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = (uint32_t)c;
+    __syncthreads();
+    if (threadIdx.x == 0) o.cnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(1024) void k_order_scan(OrderArgs o, int nblk)
+{
+    __shared__ uint32_t sc[1024];
+    const int i = threadIdx.x;
+    const uint32_t v = i < nblk ? o.cnt[i] : 0u;
+    sc[i] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = i >= off ? sc[i - off] : 0u;
+        __syncthreads();
+        sc[i] += add;
+        __syncthreads();
+    }
+    if (i < nblk) o.cnt[i] = sc[i] - v;
+    if (i < kSub) o.num[i * kPad] = 0;
+    if (i == 1023) o.num[kSub * kPad] = sc[1023];
+}
+
+__global__ __launch_bounds__(256) void k_order_write(OrderArgs o)
+{
+    __shared__ uint32_t ws[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t b0 = blockIdx.x * o.per, b1 = min(b0 + o.per, o.nb);
+    uint32_t pos = o.cnt[blockIdx.x];
+    for (uint32_t c0 = b0; c0 < b1; c0 += 256) {
+        const uint32_t b = c0 + threadIdx.x;
+        const bool m = b < b1 && o.stamp[b] == o.val;
+        const unsigned long long bal = __ballot(m);
+        if (lane == 0) ws[wave] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < wave; ++k) before += ws[k];
+        if (m) o.out[pos + before + __popcll(bal & ((1ull << lane) - 1ull))] = bpack_lin((int)b, o.nb1);
+        pos += ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
     }
 }
 
@@ -1642,6 +1718,7 @@ struct ebit_ctx {
     const void *lastC;     // C array of the previous Front2VOF
     int surr;              // the surrogate is set (weights image in w.simg); 0: geometric Front2VOF only
     int fuse;              // ebit_advance launches a Front2VOF with the next x sweep
+    int order;             // each sweep's band list is put in brick order first
     int timing;            // bracket every timing-th launch of each kind with events (0: off)
     unsigned tseen[3];     // launches of each kind since timing was switched on
     int tsel;              // the current launch is bracketed
@@ -1707,9 +1784,43 @@ SweepArgs<T> sweep_args(const ebit_ctx *c, const void *U, T cf)
     return a;
 }
 
+// a brick list in brick order (see OrderArgs)
+void order_list(const ebit_ctx *c, const uint32_t *stamp, uint32_t val, uint32_t *list, uint32_t *num, hipStream_t st)
+{
+    OrderArgs o;
+    o.stamp = stamp;
+    o.val = val;
+    o.out = list + (size_t)kSub * c->g.scap;
+    o.num = num;
+    o.cnt = c->w.ocnt;
+    o.nb = (uint32_t)c->g.nb;
+    o.per = (o.nb + kOrderBlocks - 1) / kOrderBlocks;
+    o.nb1 = c->g.nb1;
+    const int nblk = (int)((o.nb + o.per - 1) / o.per);
+    hipLaunchKernelGGL(k_order_count, dim3(nblk), dim3(256), 0, st, o);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, o, nblk);
+    hipLaunchKernelGGL(k_order_write, dim3(nblk), dim3(256), 0, st, o);
+}
+
+// the band list of the next sweep (c->t)
+void order_band(const ebit_ctx *c, hipStream_t st)
+{
+    if (!c->order || c->full) return;
+    const uint32_t t = c->t;
+    order_list(c, c->w.cm, t, c->w.blist[t % 4], c->w.bnum + (t % 4) * kNum * kPad, st);
+}
+
+// the revisit list of Front2VOF generation gen (not for a full Front2VOF)
+void order_revisit(const ebit_ctx *c, uint32_t gen, int full, hipStream_t st)
+{
+    if (!c->order || full) return;
+    order_list(c, c->w.fmark, gen, c->w.flist[gen % 3], c->w.fnum + (gen % 3) * kNum * kPad, st);
+}
+
 template <typename T, int D>
 void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
 {
+    order_band(c, st);
     const SweepArgs<T> a = sweep_args<T>(c, U, cf);
     time_begin(c, st, 0);
     hipLaunchKernelGGL((k_sweep<T, D>), dim3(c->g.nw), dim3(64), 0, st, a);
@@ -1749,6 +1860,7 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     int full = c->full || C != c->lastC;
     if (!full && c->last_t_f2v == c->t) return EBIT_OK;   // nothing moved since the last call
     const F2VArgs<T> a = f2v_args<T>(c, C, full);
+    order_revisit(c, c->fgen, full, st);
     time_begin(c, st, 1);
     hipLaunchKernelGGL((k_f2v<T>), dim3(c->g.nw), dim3(64), 0, st, a, c->surr ? 1 : 0);
     if (c->surr)
@@ -1771,6 +1883,8 @@ int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, 
     c->last_t_f2v = c->t;
     c->lastC = C;
     const SweepArgs<T> a = sweep_args<T>(c, Ux, (T)((dt * (double)c->n) * g));
+    order_revisit(c, f.gen, f.full, st);
+    order_band(c, st);
     time_begin(c, st, 2);
     hipLaunchKernelGGL((k_f2v_sweep_x<T>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
     time_end(c, st, 2);
@@ -1890,6 +2004,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->lastC = nullptr;
     c->surr = 0;
     c->fuse = 1;
+    c->order = d->n >= EBIT_ORDER_MIN_N;
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
@@ -2034,6 +2149,10 @@ int ebit_set_option(ebit_ctx *c, int option, int value)
     }
     if (option == EBIT_OPT_FUSE) {
         c->fuse = value != 0;
+        return EBIT_OK;
+    }
+    if (option == EBIT_OPT_ORDER) {
+        c->order = value != 0;
         return EBIT_OK;
     }
     if (option == EBIT_OPT_SUBLIST_CAP) {

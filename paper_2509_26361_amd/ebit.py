@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libebit.so")
 
 EBIT_OK, EBIT_EINVAL, EBIT_ECFL, EBIT_ESTATE, EBIT_EHIP, EBIT_ENOSURR, EBIT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 EBIT_FP64, EBIT_FP32 = 0, 1
-EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING, EBIT_OPT_FUSE, EBIT_OPT_SUBLIST_CAP = 1, 2, 3, 4
+EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING, EBIT_OPT_FUSE, EBIT_OPT_SUBLIST_CAP, EBIT_OPT_ORDER = 1, 2, 3, 4, 5
 
 _lib = None
 
