@@ -63,3 +63,38 @@ def test_bad_arguments_rejected_on_host(lib):
     assert L.ebit_advect_sweep(None, 0, None, 1.0, 0.1, None) == E.EBIT_EINVAL
     assert L.ebit_front2vof(None, None, None) == E.EBIT_EINVAL
     assert L.ebit_strerror(E.EBIT_ECFL).decode().startswith("Courant")
+
+
+def test_mlp_entry_points_reject_bad_arguments_on_host(lib):
+    """ebit_mlp_gradient / ebit_mlp_train argument checks (the pointers are
+    never dereferenced: every call returns before any GPU work)."""
+    from paper_2509_26361_amd import ebit as E
+    L = E.lib()
+    P = ctypes.c_void_p
+    need = L.ebit_mlp_scratch_bytes()
+    assert need > 256 * L.ebit_mlp_param_count() * 4        # partial sums of 256 workgroups and more
+    ok, odd = P(4096), P(4100)                                # aligned / not 16-byte aligned
+    lr = (ctypes.c_float * 4)(1e-3, 1e-3, 1e-3, 1e-3)
+    lrp = ctypes.cast(lr, P)
+
+    def train(theta=ok, x=ok, c=ok, nrows=100, idx=ok, batch=10, steps=4, lrs=lrp, step0=0, scratch=ok,
+              nbytes=need):
+        return L.ebit_mlp_train(theta, ok, ok, x, c, nrows, idx, batch, steps, lrs, step0, None, scratch, nbytes,
+                                None)
+
+    assert train(steps=0) == E.EBIT_OK                        # nothing to do
+    assert train(theta=None) == E.EBIT_EINVAL
+    assert train(x=None) == E.EBIT_EINVAL
+    assert train(nrows=0) == E.EBIT_EINVAL
+    assert train(batch=0) == E.EBIT_EINVAL
+    assert train(steps=-1) == E.EBIT_EINVAL
+    assert train(step0=-1) == E.EBIT_EINVAL
+    assert train(lrs=None) == E.EBIT_EINVAL
+    assert train(idx=None, batch=101) == E.EBIT_EINVAL         # rows 0..batch-1 must exist
+    assert train(scratch=None) == E.EBIT_EINVAL
+    assert train(scratch=odd) == E.EBIT_EINVAL
+    assert train(nbytes=need - 1) == E.EBIT_ESCRATCH
+    assert L.ebit_mlp_gradient(ok, ok, ok, 10, ok, None, odd, need, None) == E.EBIT_EINVAL
+    assert L.ebit_mlp_gradient(ok, ok, ok, 10, ok, None, ok, need - 16, None) == E.EBIT_ESCRATCH
+    assert L.ebit_mlp_gradient(ok, ok, ok, 0, ok, None, ok, need, None) == E.EBIT_EINVAL
+    assert L.ebit_mlp_adam(ok, ok, ok, ok, 0, 1e-3, None) == E.EBIT_EINVAL
