@@ -86,7 +86,7 @@ constexpr int kClaimCap = 16;     // sweep: queued bricks whose neighbours join 
 #endif
 constexpr int kSurrWaves = EBIT_SURR_WAVES;   // waves per block of the surrogate pass (sharing the weights)
 #ifndef EBIT_SURR_BLOCKS
-#define EBIT_SURR_BLOCKS 256   // one block (weights in 85 KB of LDS) per CU, each looping over segments
+#define EBIT_SURR_BLOCKS 256   // one block (weights and tiles in 124 KB of LDS) per CU, each looping over segments
 #endif
 #ifndef EBIT_BATCH
 #define EBIT_BATCH 2
