@@ -163,7 +163,7 @@ def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the library and this benchmark run on one GPU; several GPUs are not supported",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
