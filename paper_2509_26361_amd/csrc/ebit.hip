@@ -323,6 +323,24 @@ __device__ __forceinline__ uint32_t item_of(uint32_t w, uint32_t i, uint32_t nw)
     return ((idx / kXcdChunk) * 8u + x) * kXcdChunk + idx % kXcdChunk;
 }
 
+// The items of wave w when the list is in brick order: XCD x takes the x-th
+// eighth of the list, its waves equal consecutive runs of it, so that an XCD
+// works on one region and a wave on neighbouring bricks, whose task stencils
+// share cache lines.  Past the wave's run: ~0u.
+struct Runs {
+    uint32_t first, len;   // the wave's run: items first .. first + len - 1
+    __device__ __forceinline__ void init(uint32_t w, uint32_t nw, uint32_t total)
+    {
+        const uint32_t x = w & 7u, j = w >> 3, nj = nw >> 3;
+        const uint32_t cx = __builtin_amdgcn_readfirstlane((total + 7u) / 8u);
+        const uint32_t cw = __builtin_amdgcn_readfirstlane((cx + nj - 1u) / nj);
+        const uint32_t r0 = min(j * cw, cx), r1 = min(r0 + cw, cx);
+        first = x * cx + r0;
+        len = r1 - r0;
+    }
+    __device__ __forceinline__ uint32_t item(uint32_t i) const { return i < len ? first + i : ~0u; }
+};
+
 // Items of a grid: the entries of a list, its kSub sub-lists and then its
 // overflow sub-list.  The inclusive prefix sums of the sub-list lengths are
 // kept in LDS (pre[0..kSub)).
@@ -536,6 +554,7 @@ struct SweepArgs {
     uint32_t t;       // sweep sequence number (>= 2)
     uint32_t fgen;    // generation of the next Front2VOF
     int full;         // process every brick
+    int run;          // the list is in brick order: waves take runs of it (Runs)
 };
 
 // Brick tile: flags and advected coordinate of the D-edge markers of the
@@ -602,7 +621,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
 // corners; the rest is queued.  The bricks next to a brick holding markers
 // join the next sweep's list; bricks whose cells change join the next
 // Front2VOF's list.
-template <typename T, int D>
+template <typename T, int D, int RUN>
 __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, const int nw)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
@@ -670,10 +689,14 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     // this wave's items item_of(wv, i), resolved one per lane (a static
     // schedule: a shared counter handing out items cost more than the
     // imbalance it removes)
-    for (uint32_t i0 = 0; item_of((uint32_t)wv, i0, (uint32_t)nw) < it.total; i0 += 64) {
+    // RUN (the list is in brick order): the wave's run of the list; else item_of
+    Runs ru;
+    if (RUN) ru.init((uint32_t)wv, (uint32_t)nw, it.total);
+    auto item = [&](uint32_t i) { return RUN ? ru.item(i) : item_of((uint32_t)wv, i, (uint32_t)nw); };
+    for (uint32_t i0 = 0; item(i0) < it.total; i0 += 64) {
         int bl = -1;
         {
-            const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
+            const uint32_t k = item(i0 + (uint32_t)lane);
             const bool have = k < it.total;
             // packed brick coordinates (-1: none)
             int bb = a.full ? (have ? (int)bpack_lin((int)k, nb1) : -1) : it.brick_lane(have ? k : 0);
@@ -949,10 +972,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     }
 }
 
-template <typename T, int D>
+template <typename T, int D, int RUN>
 __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_sweep(SweepArgs<T> a)
 {
-    sweep_wave<T, D>(a, blockIdx.x, gridDim.x);
+    sweep_wave<T, D, RUN>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1401,11 +1424,11 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
 // independent.  The sweep's workgroups come first and fill the chip; the
 // Front2VOF's start as sweep waves retire and fill the sweep's tail (both
 // parts have a multiple of 8 waves, so each keeps its XCD-aware mapping).
-template <typename T>
+template <typename T, int RUN>
 __global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_f2v_sweep_x(SweepArgs<T> s, F2VArgs<T> f)
 {
     const int b = blockIdx.x, nw = s.g.nw;
-    if (b < nw) sweep_wave<T, 0>(s, b, nw);
+    if (b < nw) sweep_wave<T, 0, RUN>(s, b, nw);
     else f2v_wave<T>(f, 0, b - nw, nw);
 }
 
@@ -1781,6 +1804,7 @@ SweepArgs<T> sweep_args(const ebit_ctx *c, const void *U, T cf)
     a.t = c->t;
     a.fgen = c->fgen;
     a.full = c->full;
+    a.run = c->order && !c->full;
     return a;
 }
 
@@ -1823,7 +1847,8 @@ void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
     order_band(c, st);
     const SweepArgs<T> a = sweep_args<T>(c, U, cf);
     time_begin(c, st, 0);
-    hipLaunchKernelGGL((k_sweep<T, D>), dim3(c->g.nw), dim3(64), 0, st, a);
+    if (a.run) hipLaunchKernelGGL((k_sweep<T, D, 1>), dim3(c->g.nw), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_sweep<T, D, 0>), dim3(c->g.nw), dim3(64), 0, st, a);
     time_end(c, st, 0);
 }
 
@@ -1886,7 +1911,8 @@ int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, 
     order_revisit(c, f.gen, f.full, st);
     order_band(c, st);
     time_begin(c, st, 2);
-    hipLaunchKernelGGL((k_f2v_sweep_x<T>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
+    if (a.run) hipLaunchKernelGGL((k_f2v_sweep_x<T, 1>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
+    else hipLaunchKernelGGL((k_f2v_sweep_x<T, 0>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
     time_end(c, st, 2);
     c->t++;
     c->cur ^= 1;
