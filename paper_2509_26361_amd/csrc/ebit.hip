@@ -1228,6 +1228,7 @@ struct F2VArgs {
     Work w;
     uint32_t gen;     // this Front2VOF's generation
     int full;
+    int run;          // the list is in brick order: waves take runs of it (Runs)
 };
 
 // node indices of the 8 corners of cell (x, y, z) (corner k = ox + 2 oy + 4 oz)
@@ -1338,12 +1339,16 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
     long np = 0;
     int nq = 0, ambc = 0;
     long long delta = 0;
-    // this wave's items item_of(wv, i) (static: the wave's interfacial-cell
-    // segment holds the at most ceil(nb / nw) + 2 bricks), resolved one per lane
-    for (uint32_t i0 = 0; item_of((uint32_t)wv, i0, (uint32_t)nw) < it.total; i0 += 64) {
+    // this wave's items, item_of(wv, i) or its run of an ordered list (static:
+    // the wave's interfacial-cell segment holds the at most ceil(nb / nw) + 2
+    // bricks either gives), resolved one per lane
+    Runs ru;
+    if (a.run) ru.init((uint32_t)wv, (uint32_t)nw, it.total);
+    auto item = [&](uint32_t i) { return a.run ? ru.item(i) : item_of((uint32_t)wv, i, (uint32_t)nw); };
+    for (uint32_t i0 = 0; item(i0) < it.total; i0 += 64) {
         int bl = -1;
         {
-            const uint32_t k = item_of((uint32_t)wv, i0 + (uint32_t)lane, (uint32_t)nw);
+            const uint32_t k = item(i0 + (uint32_t)lane);
             const bool have = k < it.total;
             int bb = a.full ? (have ? (int)bpack_lin((int)k, nb1) : -1) : it.brick_lane(have ? k : 0);
             if (!have || bb < 0 || bx_of((uint32_t)bb) >= nb1 || by_of((uint32_t)bb) >= nb1 || bz_of((uint32_t)bb) >= nb1)
@@ -1863,6 +1868,7 @@ F2VArgs<T> f2v_args(const ebit_ctx *c, void *C, int full)
     a.w = c->w;
     a.gen = c->fgen;
     a.full = full;
+    a.run = c->order && !full;
     return a;
 }
 
