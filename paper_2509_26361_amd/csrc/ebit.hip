@@ -567,8 +567,12 @@ constexpr int kAD = 6, kAA = 5, kATile = kAD * kAA * kAA;
 // face's colour, and with type bit 1 the circle-fit placement of the node's
 // new marker on the edge across (whose end colours differ, so the face's
 // corners do too); bit 2 is the node's new colour.  Face colours are gathered
-// per node in the slot table and the node's flags byte is written once.
-template <typename T, int D>
+// per node in the slot table and the node's flags byte is written once.  RUN
+// (large grids, ordered lists): the tasks' first load round reads only the
+// entries of existing markers -- fewer cache lines where the traffic bounds
+// the sweep, at the price of registers that the small grids' latency-bound
+// sweep is better without.
+template <typename T, int D, int RUN>
 __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t *tq, const uint8_t *tt,
                                           const uint16_t *ts, int ntask, const uint32_t *sq, uint32_t *sb,
                                           int nslot, int &fbt, int &multit)
@@ -586,7 +590,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
             const bool second = ty & 1;             // plane (D, A2)
             const int unal = (ty >> 1) & 1, c00 = (ty >> 2) & 1;
             const int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / nn)};
-            PlaneTask<T, D> p;
+            PlaneTask<T, D, RUN> p;
             p.fl = a.fl;
             p.sD = a.s[D];
             p.sA = second ? a.s[A2] : a.s[A1];
@@ -846,7 +850,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             if (skipj) continue;
             if (!quietj && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
             if (ntask + 2 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
-                run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
+                run_tasks<T, D, RUN>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
                 nslot = 0;
             }
@@ -954,7 +958,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             __syncthreads();   // the tiles are reused by the next batch
         }
     }
-    run_tasks<T, D>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
+    run_tasks<T, D, RUN>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
     claims();
     // this wave's counters (the wave owns its slot)
     fbc = wave_sum(fbc + fbt);

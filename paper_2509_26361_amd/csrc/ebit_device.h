@@ -102,7 +102,9 @@ __device__ __forceinline__ T fit_height(T P1x, T P1y, T P2x, T P2y, T P3x, T P3y
 // independent loads: the flags of offsets i in [-3, 2], j in [-1, 2]; then the
 // markers of the three candidate faces; then, for a new unaligned marker, the
 // two polyline neighbours of the chosen segment.
-template <typename T, int D>
+// SPARSE: the first round reads only the entries of existing markers (fewer
+// cache lines fetched; more registers)
+template <typename T, int D, int SPARSE>
 struct PlaneTask {
     const uint8_t *__restrict__ fl;
     const T *__restrict__ sD;     // fractions of the H markers
@@ -224,8 +226,7 @@ struct PlaneTask {
     // V(0,0) differ): the new marker on V(0,0) -- crossings of X = 0 by the
     // advected old segments of faces -2..0 of the row, the median one (by
     // height) refined by the circle fit (*sval).  Faces -2..1 of the row share
-    // one round of loads, issued before any arithmetic (a missing marker reads
-    // a valid entry and is masked).
+    // one round of loads, issued before any arithmetic.
     __device__ __forceinline__ int run(int unal, int c00, T &sval, int &fallback, int &multi) const
     {
         // velocities at nodes (k - 2, r), k = 0..4, r = 0, 1; fractions of H(f - 2, r),
@@ -235,17 +236,22 @@ struct PlaneTask {
         for (int k = 0; k < 5; ++k)
 #pragma unroll
             for (int r = 0; r < 2; ++r) qn[k][r] = xo[k + 1] + yo[r + 1];
+        // every entry (a missing marker reads a valid entry, masked below), or
+        // with SPARSE only those of existing markers (the others stay 0)
         T Un[5][2], sh_[4][2], sv_[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) Un[k][r] = U[qn[k][r]];
+            for (int r = 0; r < 2; ++r) {
+                const bool need = (k < 4 && hhas(k - 2, r)) || (k > 0 && hhas(k - 3, r)) || vhas(k - 2, 0);
+                Un[k][r] = !SPARSE || need ? U[qn[k][r]] : T(0);
+            }
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) sh_[f][r] = sD[qn[f][r]];
+            for (int r = 0; r < 2; ++r) sh_[f][r] = !SPARSE || hhas(f - 2, r) ? sD[qn[f][r]] : T(0);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) sv_[k] = sA[qn[k][0]];
+        for (int k = 0; k < 5; ++k) sv_[k] = !SPARSE || vhas(k - 2, 0) ? sA[qn[k][0]] : T(0);
         // advected markers (X, Y relative to the node)
         double Hx[4][2], Vx[5], Vy[5];
 #pragma unroll
