@@ -1,0 +1,91 @@
+"""The large mixed workload at full size: 512^3, 4096 seeded spheres (radii
+3..12 cells) in a seeded divergence-free Fourier field, CFL 0.5, run by
+ebit_advance with its defaults for this size (brick-ordered lists, waves on
+contiguous runs of them, sparse task loads, Front2VOF fused with the next x
+sweep).
+
+The oracle cannot take a step of this grid in seconds.  What holds at any
+size is checked instead:
+- the run equals, bit for bit, the same run with lists in claim order (the
+  kernels whose oracle parity the smaller tests establish);
+- the state is consistent: an edge carries a marker exactly where its end
+  colours differ (sec. 2.2), and every fraction lies in [0, 1);
+- the interfacial-cell counter agrees with the flags."""
+import pytest
+import torch
+
+from paper_2509_26361_amd import ebit as E
+from paper_2509_26361_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+N = 512
+STEPS = 12
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def workload():
+    d = dev()
+    free, total = torch.cuda.mem_get_info(d)
+    if total < 64 * 2**30:
+        pytest.skip("needs a GPU with about 40 GB")
+    cs, rs = I.random_nonoverlapping_spheres(4096, 3.0, 12.0, N, gap_cells=2.0, seed=0)
+    sh = I.spheres_shape(N, cs, rs, with_s=False)
+    phi = torch.from_numpy(sh.phi_nodes).to(d)
+    pf = [torch.from_numpy(f).to(d) for f in sh.phi_faces]
+    del sh
+    U = I.fourier_velocity_device(N, seed=1, modes=8, device=d)
+    return phi, pf, U
+
+
+def run(workload, order):
+    phi, pf, U = workload
+    e = E.Ebit(N, "fp64", dev())
+    e.init(phi, pf)
+    if order is not None:
+        e.set_option(E.EBIT_OPT_ORDER, order)
+    C = torch.zeros((N, N, N), dtype=torch.float64, device=dev())
+    e.front2vof(C)
+    e.advance(U, [1.0] * STEPS, 0.5 / N, C)
+    torch.cuda.synchronize()
+    return e, C
+
+
+def test_mixed_512_ordered_run_equals_claim_order_and_is_consistent(workload):
+    a, Ca = run(workload, None)           # the default at this size: ordered
+    fa, sa = a.state()
+    st_a = a.stats(Ca)
+    b, Cb = run(workload, 0)
+    fb, sb = b.state()
+    assert torch.equal(fa, fb)
+    for k in range(3):
+        assert torch.equal(sa[k], sb[k]), k
+    assert torch.equal(Ca, Cb)
+    st_b = b.stats(Cb)
+    for key in ("n_interfacial", "n_interfacial_sum", "n_fallback", "n_cfl", "volume", "volume_comp"):
+        assert st_a[key] == st_b[key], key
+    del b, Cb, fb, sb
+    torch.cuda.empty_cache()
+
+    # edge markers exactly where the end colours differ (x fastest: tensor dim 2 - e)
+    col = fa & 1
+    for e in range(3):
+        m = (fa >> (4 + e)) & 1
+        differ = (col != torch.roll(col, -1, 2 - e)).to(torch.uint8)
+        assert torch.equal(m, differ), f"axis {e}: {int((m != differ).sum())} inconsistent edges"
+        s = sa[e][m.bool()]
+        assert bool(((s >= 0) & (s < 1)).all()), f"axis {e}: fraction outside [0, 1)"
+    assert st_a["n_cfl"] == 0
+    # interfacial cells: a marker on any of the cell's 12 edges
+    has = torch.zeros_like(col, dtype=torch.bool)
+    for e in range(3):
+        m = ((fa >> (4 + e)) & 1).bool()
+        a1, a2 = [2 - x for x in range(3) if x != e]
+        has |= m | torch.roll(m, -1, a1) | torch.roll(m, -1, a2) | torch.roll(torch.roll(m, -1, a1), -1, a2)
+    assert st_a["n_interfacial"] == int(has.sum())
+    assert st_a["n_interfacial"] > 4_000_000
