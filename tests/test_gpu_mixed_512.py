@@ -11,6 +11,7 @@ size is checked instead:
 - the state is consistent: an edge carries a marker exactly where its end
   colours differ (sec. 2.2), and every fraction lies in [0, 1);
 - the interfacial-cell counter agrees with the flags."""
+import numpy as np
 import pytest
 import torch
 
@@ -43,15 +44,18 @@ def workload():
     return phi, pf, U
 
 
-def run(workload, order):
+def run(workload, order, prec="fp64", theta=None):
     phi, pf, U = workload
-    e = E.Ebit(N, "fp64", dev())
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    e = E.Ebit(N, prec, dev())
     e.init(phi, pf)
     if order is not None:
         e.set_option(E.EBIT_OPT_ORDER, order)
-    C = torch.zeros((N, N, N), dtype=torch.float64, device=dev())
+    if theta is not None:
+        e.set_surrogate(theta)
+    C = torch.zeros((N, N, N), dtype=dtype, device=dev())
     e.front2vof(C)
-    e.advance(U, [1.0] * STEPS, 0.5 / N, C)
+    e.advance([u.to(dtype) for u in U], [1.0] * STEPS, 0.5 / N, C)
     torch.cuda.synchronize()
     return e, C
 
@@ -89,3 +93,20 @@ def test_mixed_512_ordered_run_equals_claim_order_and_is_consistent(workload):
         has |= m | torch.roll(m, -1, a1) | torch.roll(m, -1, a2) | torch.roll(torch.roll(m, -1, a1), -1, a2)
     assert st_a["n_interfacial"] == int(has.sum())
     assert st_a["n_interfacial"] > 4_000_000
+
+
+@pytest.mark.parametrize("surrogate", [False, True])
+def test_mixed_512_fp32_forms_ordered_equal_claim_order(workload, surrogate):
+    """The FP32 form, and the FP32 form with the surrogate (a seeded untrained
+    network: the test is about the lists, not the network), at full size:
+    ordered lists bit-identical to claim order."""
+    theta = torch.from_numpy(I.mlp_init(3).astype(np.float32)).to(dev()) if surrogate else None
+    a, Ca = run(workload, None, "fp32", theta)
+    fa, sa = a.state()
+    b, Cb = run(workload, 0, "fp32", theta)
+    fb, sb = b.state()
+    assert torch.equal(fa, fb)
+    for k in range(3):
+        assert torch.equal(sa[k], sb[k]), k
+    assert torch.equal(Ca, Cb)
+    assert a.stats(Ca)["n_interfacial_sum"] == b.stats(Cb)["n_interfacial_sum"]
