@@ -149,9 +149,10 @@ int ebit_current(const ebit_ctx *ctx);
  * sweeps along x, y and z (ebit_advect_sweep with time factor g[k] and step
  * dt, the time level of the step for all three, sec. 2.3), then Front2VOF
  * into C (ebit_front2vof) unless C is NULL.  With EBIT_OPT_FUSE on (the
- * default) and no surrogate set, the Front2VOF of step k < nsteps - 1 runs
- * in one launch with the x sweep of step k + 1 (same results; C is complete
- * when the enqueued work ends).
+ * default), the Front2VOF of step k < nsteps - 1 runs in one launch with the
+ * x sweep of step k + 1 -- with a surrogate set, its classify pass, the
+ * network's pass following that launch (same results; C is complete when
+ * the enqueued work ends).
  *   U       3 device pointers: U_x, U_y, U_z (n^3 each, the precision's type)
  *   g       host array of nsteps time factors
  * Returns the first error of the calls it makes (the steps before it are

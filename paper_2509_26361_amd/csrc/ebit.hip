@@ -1434,11 +1434,11 @@ __global__ __launch_bounds__(64, EBIT_F2V_WAVES) void k_f2v(F2VArgs<T> a, int cl
 // Front2VOF's start as sweep waves retire and fill the sweep's tail (both
 // parts have a multiple of 8 waves, so each keeps its XCD-aware mapping).
 template <typename T, int RUN>
-__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_f2v_sweep_x(SweepArgs<T> s, F2VArgs<T> f)
+__global__ __launch_bounds__(64, EBIT_SWEEP_WAVES) void k_f2v_sweep_x(SweepArgs<T> s, F2VArgs<T> f, int classify)
 {
     const int b = blockIdx.x, nw = s.g.nw;
     if (b < nw) sweep_wave<T, 0, RUN>(s, b, nw);
-    else f2v_wave<T>(f, 0, b - nw, nw);
+    else f2v_wave<T>(f, classify, b - nw, nw);
 }
 
 
@@ -1908,8 +1908,11 @@ int f2v_impl(ebit_ctx *c, void *C, hipStream_t st)
     return check_launch();
 }
 
-// Front2VOF into C (geometric, after at least one sweep) and then the x sweep
-// of the next step, as one launch of k_f2v_sweep_x.
+// Front2VOF into C (after at least one sweep) and then the x sweep of the
+// next step, as one launch of k_f2v_sweep_x.  With the surrogate set, the
+// launch holds its classify pass and the network's pass follows: it reads
+// the state the x sweep left untouched (the sweep writes the other buffer),
+// and the y sweep, which overwrites that state, comes after it on the stream.
 template <typename T>
 int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, hipStream_t st)
 {
@@ -1921,8 +1924,12 @@ int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, 
     order_revisit(c, f.gen, f.full, st);
     order_band(c, st);
     time_begin(c, st, 2);
-    if (a.run) hipLaunchKernelGGL((k_f2v_sweep_x<T, 1>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
-    else hipLaunchKernelGGL((k_f2v_sweep_x<T, 0>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f);
+    const int classify = c->surr ? 1 : 0;
+    if (a.run) hipLaunchKernelGGL((k_f2v_sweep_x<T, 1>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f, classify);
+    else hipLaunchKernelGGL((k_f2v_sweep_x<T, 0>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f, classify);
+    if (c->surr)
+        hipLaunchKernelGGL((k_f2v_b_surr<T>), dim3(clampi((c->g.nw + kSurrWaves - 1) / kSurrWaves, EBIT_SURR_BLOCKS)),
+                           dim3(64 * kSurrWaves), 0, st, f);
     time_end(c, st, 2);
     c->t++;
     c->cur ^= 1;
@@ -2226,8 +2233,8 @@ int ebit_advance(ebit_ctx *c, int32_t nsteps, const void *const *U, const double
 {
     if (!c || nsteps < 0 || !U || !U[0] || !U[1] || !U[2] || (nsteps > 0 && !g)) return EBIT_EINVAL;
     // a Front2VOF due before the next x sweep goes into that sweep's launch
-    // (geometric Front2VOF only: the surrogate's second pass needs the first)
-    const int fuse = C && c->fuse && !c->surr;
+    // (with the surrogate: its classify pass; the network's pass follows)
+    const int fuse = C && c->fuse;
     int pending = 0;
     for (int k = 0; k < nsteps; ++k) {
         for (int d = 0; d < 3; ++d) {

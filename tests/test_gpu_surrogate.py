@@ -143,3 +143,45 @@ def test_output_bias_calibration_matches_mean_label():
     assert abs(before - target) > 1e-2           # there was a bias to remove
     assert abs(after - target) < 2e-5, (after, target, d)
     assert torch.equal(th2[:-1], theta[:-1]) and float(th2[-1] - theta[-1]) == pytest.approx(d, abs=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_advance_with_surrogate_fused_equals_separate_launches(prec):
+    """With the surrogate set, ebit_advance puts the classify pass of each
+    Front2VOF into the next x sweep's launch and runs the network's pass
+    after it.  Against EBIT_OPT_FUSE off and against single calls (sweeps,
+    then ebit_front2vof): state, C and counters bit-identical, at a ragged
+    brick count.  The network is a seeded untrained one (the test is about
+    the launches)."""
+    n = 44
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    sh = I.sphere_shape(n, centre=(0.45, 0.5, 0.55), R=0.2)
+    U = [T(u).to(dtype) for u in I.deformation_velocity(n)]
+    theta = torch.from_numpy(I.mlp_init(5).astype(np.float32)).to(dev())
+    dt = 0.5 / n
+    gs = [I.deformation_time_factor(k * dt, 3.0) for k in range(9)]
+    out = []
+    for mode in ("fused", "unfused", "calls"):
+        e = E.Ebit(n, prec, dev())
+        e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+        e.set_surrogate(theta)
+        C = torch.zeros((n, n, n), dtype=dtype, device=dev())
+        if mode == "calls":
+            for g in gs:
+                e.step(U, g, dt)
+                e.front2vof(C)
+        else:
+            e.set_option(E.EBIT_OPT_FUSE, 1 if mode == "fused" else 0)
+            e.advance(U, gs, dt, C)
+        torch.cuda.synchronize()
+        fl, s = e.state()
+        out.append((fl.clone(), [x.clone() for x in s], C.clone(), e.stats(C)))
+    f0, s0, c0, st0 = out[0]
+    assert st0["n_interfacial"] > 0
+    for f1, s1, c1, st1 in out[1:]:
+        assert torch.equal(f0, f1)
+        for k in range(3):
+            assert torch.equal(s0[k], s1[k])
+        assert torch.equal(c0, c1)
+        for key in ("n_interfacial", "n_interfacial_sum", "n_ambiguous", "n_markers"):
+            assert st0[key] == st1[key], key
