@@ -843,12 +843,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             __syncthreads();
             for (int j = 0; j < nbat; ++j) {
             int b = bb[0];
-            bool skipj = skip[0], quietj = quiet[0];
+            bool skipj = skip[0];
+            uint32_t lastj = lastchg[0];
 #pragma unroll
             for (int u = 1; u < kBatch; ++u)
-                if (j == u) { b = bb[u]; skipj = skip[u]; quietj = quiet[u]; }
+                if (j == u) { b = bb[u]; skipj = skip[u]; lastj = lastchg[u]; }
             if (skipj) continue;
-            if (!quietj && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
             if (ntask + 2 * 64 > kTaskCap || nslot + 64 > kSlotCap) {
                 run_tasks<T, D, RUN>(a, tq, tt, ts, ntask, sq, sb, nslot, fbt, multit);
                 ntask = 0;
@@ -905,11 +905,21 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 if (task[1]) out |= (uint8_t)(1u << (4 + A2));
                 if (!task[3]) out |= (uint8_t)(c00 << (1 + A1));
             }
-            a.so[D][qs] = sdn;
-            if (!task[0]) a.so[A1][qs] = T(0);
-            if (!task[1]) a.so[A2][qs] = T(0);
             const bool fnode = task[2] || task[3];
-            if (!fnode) a.flo[qs] = out;
+            const bool hasm = __ballot((out & 0x70) != 0) != 0;
+            const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
+            // unchanged by this sweep: no marker and no face task in the brick,
+            // flags as before (its fractions are 0 then, before and after);
+            // bchg records the last sweep that changed the brick
+            const bool same = !hasm && __ballot(fnode) == 0 && __ballot(((out ^ fself) & 0x7f) != 0) == 0;
+            if (!same && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
+            // unchanged now and by the previous sweep: both buffers hold it already
+            if (!(same && !a.full && lastj + 2 <= t)) {
+                a.so[D][qs] = sdn;
+                if (!task[0]) a.so[A1][qs] = T(0);
+                if (!task[1]) a.so[A2][qs] = T(0);
+                if (!fnode) a.flo[qs] = out;
+            }
             // queue: unaligned markers of both planes, then the face nodes and their faces
             {
                 const unsigned long long lt = (1ull << lane) - 1ull;
@@ -938,11 +948,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // markers now; Front2VOF revisits the cells of bricks that hold
             // markers or whose colours / markers changed (a cell also reads the
             // edges stored at its upper neighbours)
-            const bool hasm = __ballot((out & 0x70) != 0) != 0;
-            const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
-            // a brick that is not quiet joins the next sweep's list itself
-            // (through its markers' neighbourhood when it holds markers)
-            const bool self = !hasm && !quietj;
+            // a brick this sweep changed joins the next sweep's list itself
+            // (through its markers' neighbourhood when it holds markers), so
+            // that the next sweep copies it into the other buffer
+            const bool self = !hasm && !same;
             if (lane == 0) {
                 if (hasm) mbr[nm] = (uint32_t)b;
                 if (self) sbr[ns] = (uint32_t)b;
