@@ -141,7 +141,7 @@ struct Work {
     uint32_t *cm;        // cm[b] == t <=> brick b is in the band list of sweep t (the last one it joined)
     uint32_t *fmark;     // fmark[b] == g <=> brick b is in the revisit list of Front2VOF generation g
     uint32_t *bcnt;      // interfacial cells of brick b at its last Front2VOF visit
-    uint32_t *bchg;      // last sweep at which brick b was not quiet (see k_sweep)
+    uint32_t *bchg;      // last sweep that changed brick b (see k_sweep)
     uint32_t *blist[4];  // band list of sweep t: blist[t % 4], kSub sub-lists of scap entries, overflow of nb
     uint32_t *bnum;      // [4][kNum] sub-list lengths, kPad words apart
     uint32_t *flist[3];  // revisit list of generation g: flist[g % 3]
