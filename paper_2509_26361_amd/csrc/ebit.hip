@@ -250,24 +250,30 @@ __device__ __forceinline__ void list_put(const ClaimList &L, uint32_t q, uint32_
     if (o < ocap) L.list[(size_t)kSub * scap + o] = b;
 }
 
-__device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const uint32_t *srcS, int ns,
-                                          const uint32_t *srcB, int nbr, int nb1, ClaimList A, ClaimList B, int sub,
-                                          uint32_t scap, uint32_t ocap)
+// Claims: for each brick of srcA its 27-neighbourhood, restricted by its
+// mask (NULL: none; bit d: the neighbour at offset (d % 3, d / 3 % 3, d / 9)
+// - 1 is claimed), into list A; the bricks of srcS themselves into A; for
+// each brick of srcB the 8 bricks at offsets in {-1, 0}^3 into list B.
+__device__ __forceinline__ void claim_two(const uint32_t *srcA, const uint32_t *maskA, int na, const uint32_t *srcS,
+                                          int ns, const uint32_t *srcB, int nbr, int nb1, ClaimList A, ClaimList B,
+                                          int sub, uint32_t scap, uint32_t ocap)
 {
     const int lane = threadIdx.x & 63;
     const int ta = na * 27 + ns, total = ta + nbr * 8;
     for (int base = 0; base < total; base += 256) {
         uint32_t nbk[4];
-        bool take[4], inA[4];
+        bool take[4], inA[4], use[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = base + 64 * u + lane;
             take[u] = false;
             inA[u] = c < ta;
+            use[u] = c < total;
             nbk[u] = 0;
             if (c < na * 27) {
                 const uint32_t b = srcA[c / 27];
                 const int d = c % 27;
+                if (maskA && !((maskA[c / 27] >> d) & 1u)) use[u] = false;
                 nbk[u] = brick_shift(b, nb1, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1);
             } else if (c < ta) {
                 nbk[u] = srcS[c - na * 27];
@@ -279,7 +285,7 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, int na, const ui
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (base + 64 * u + lane >= total) continue;
+            if (!use[u]) continue;
             const ClaimList &L = inA[u] ? A : B;
             take[u] = atomicExch(&L.mark[blin(nbk[u], nb1)], L.v) != L.v;
         }
@@ -444,7 +450,8 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         if (hasm) {
             const ClaimList A{w.cm, 2u, w.blist[2], w.bnum + 2 * kNum * kPad};
             const uint32_t bp = bpack(bx, by, bz);
-            claim_two(&bp, 1, nullptr, 0, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap, (uint32_t)g.nb);
+            claim_two(&bp, nullptr, 1, nullptr, 0, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap,
+                      (uint32_t)g.nb);
         }
     }
 }
@@ -555,6 +562,7 @@ struct SweepArgs {
     uint32_t fgen;    // generation of the next Front2VOF
     int full;         // process every brick
     int run;          // the list is in brick order: waves take runs of it (Runs)
+    int nd;           // axis of the next sweep when known (ebit_advance), else -1
 };
 
 // Brick tile: flags and advected coordinate of the D-edge markers of the
@@ -636,6 +644,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint16_t ts[kTaskCap];
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap], sbr[kClaimCap];
+    __shared__ uint32_t mmk[kClaimCap];
     __shared__ uint32_t ipre[kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
@@ -683,7 +692,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
     auto claims = [&]() {
         __syncthreads();
-        claim_two(mbr, nm, sbr, ns, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
+        claim_two(mbr, mmk, nm, sbr, ns, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
                   ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)a.g.scap, (uint32_t)nb);
         __syncthreads();
         nm = 0;
@@ -952,8 +961,32 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // (through its markers' neighbourhood when it holds markers), so
             // that the next sweep copies it into the other buffer
             const bool self = !hasm && !same;
+            // the neighbours the next sweep can change from this brick's
+            // markers: along its axis D' nodes -2..+1 from a marker's node,
+            // across it -1..0 (landing edges, crossed nodes, the edges across
+            // whose end colours change, the face colours that read the
+            // segments of three faces); unknown next axis: all 26
+            uint32_t m27 = 0x7ffffffu;
+            if (hasm && a.nd >= 0) {
+                // lanes whose node has local coordinate 0, <= 1, 3 along axis e
+                // (lane = x + 4 y + 16 z)
+                constexpr unsigned long long k0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
+                constexpr unsigned long long k1[3] = {0x3333333333333333ull, 0x00FF00FF00FF00FFull, 0xFFFFFFFFull};
+                constexpr unsigned long long k3[3] = {0x8888888888888888ull, 0xF000F000F000F000ull,
+                                                      0xFFFF000000000000ull};
+                const int Dn = a.nd, An = (Dn + 1) % 3, Bn = (Dn + 2) % 3;
+                const unsigned long long mb = __ballot((out & 0x70) != 0);
+                // allowed offsets per axis: bit 0 -1, bit 1 0, bit 2 +1
+                int al[3];
+                al[Dn] = 2 | ((mb & k1[Dn]) != 0 ? 1 : 0) | ((mb & k3[Dn]) != 0 ? 4 : 0);
+                al[An] = 2 | ((mb & k0[An]) != 0 ? 1 : 0);
+                al[Bn] = 2 | ((mb & k0[Bn]) != 0 ? 1 : 0);
+                m27 = 0;
+                for (int d = 0; d < 27; ++d)
+                    if (((al[0] >> (d % 3)) & (al[1] >> (d / 3 % 3)) & (al[2] >> (d / 9))) & 1) m27 |= 1u << d;
+            }
             if (lane == 0) {
-                if (hasm) mbr[nm] = (uint32_t)b;
+                if (hasm) { mbr[nm] = (uint32_t)b; mmk[nm] = m27; }
                 if (self) sbr[ns] = (uint32_t)b;
                 if (hasm || chg) cbr[nc] = (uint32_t)b;
             }
@@ -1760,6 +1793,7 @@ struct ebit_ctx {
     int surr;              // the surrogate is set (weights image in w.simg); 0: geometric Front2VOF only
     int fuse;              // ebit_advance launches a Front2VOF with the next x sweep
     int order;             // each sweep's band list is put in brick order first
+    int next_dir;          // axis of the sweep after the one being launched, -1 if not known
     int timing;            // bracket every timing-th launch of each kind with events (0: off)
     unsigned tseen[3];     // launches of each kind since timing was switched on
     int tsel;              // the current launch is bracketed
@@ -1823,6 +1857,7 @@ SweepArgs<T> sweep_args(const ebit_ctx *c, const void *U, T cf)
     a.fgen = c->fgen;
     a.full = c->full;
     a.run = c->order && !c->full;
+    a.nd = c->next_dir;
     return a;
 }
 
@@ -2057,6 +2092,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->surr = 0;
     c->fuse = 1;
     c->order = d->n >= EBIT_ORDER_MIN_N;
+    c->next_dir = -1;
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
@@ -2248,14 +2284,18 @@ int ebit_advance(ebit_ctx *c, int32_t nsteps, const void *const *U, const double
     for (int k = 0; k < nsteps; ++k) {
         for (int d = 0; d < 3; ++d) {
             int rc;
+            // the sweep after this one (known within the call): its band takes
+            // only the neighbours it can change
+            c->next_dir = d < 2 ? d + 1 : (k + 1 < nsteps ? 0 : -1);
             if (d == 0 && pending) {
-                if (!(dt >= 0.0) || !isfinite(g[k])) return EBIT_EINVAL;
-                rc = c->precision == EBIT_FP64 ? f2v_sweep_x_impl<double>(c, C, U[0], g[k], dt, S(stream))
-                                               : f2v_sweep_x_impl<float>(c, C, U[0], g[k], dt, S(stream));
+                if (!(dt >= 0.0) || !isfinite(g[k])) rc = EBIT_EINVAL;
+                else rc = c->precision == EBIT_FP64 ? f2v_sweep_x_impl<double>(c, C, U[0], g[k], dt, S(stream))
+                                                    : f2v_sweep_x_impl<float>(c, C, U[0], g[k], dt, S(stream));
                 pending = 0;
             } else {
                 rc = ebit_advect_sweep(c, d, U[d], g[k], dt, stream);
             }
+            c->next_dir = -1;
             if (rc != EBIT_OK) return rc;
         }
         if (C) {

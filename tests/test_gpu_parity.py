@@ -386,3 +386,51 @@ def test_brick_ordered_lists_give_same_results(prec, n):
         assert np.array_equal(c0, c1)
         for key in ("n_interfacial_sum", "n_active_cells", "n_interfacial", "n_fallback"):
             assert st0[key] == st1[key], key
+
+
+@pytest.mark.parametrize("case", ["random48", "deformation40", "translation36"])
+def test_advance_directional_band_equals_single_calls(case):
+    """Inside ebit_advance the next sweep's axis is known, and a brick with
+    markers adds to the next band only the neighbours that sweep can change
+    (along its axis nodes -2..+1 of a marker, across it -1..0).  Single calls
+    do not know the next axis and add all 26 neighbours.  Over long runs with
+    many topology events the two must agree bit for bit: state, C, counters."""
+    if case == "random48":
+        n, steps = 48, 60
+        sh = I.random_shape(n, seed=11)
+        U = [T(u) for u in I.fourier_velocity(n, seed=12)]
+        gs = [1.0] * steps
+    elif case == "deformation40":
+        n = 40
+        steps = 6 * n            # the whole period, T = 3 at CFL 0.5
+        sh = I.sphere_shape(n, centre=(0.35, 0.35, 0.35), R=0.15)
+        U = [T(u) for u in I.deformation_velocity(n)]
+        gs = [I.deformation_time_factor(k * 0.5 / n, 3.0) for k in range(steps)]
+    else:
+        n, steps = 36, 40
+        sh = I.sphere_shape(n, centre=(0.3, 0.45, 0.6), R=0.2)
+        U = [T(np.full((n, n, n), v)) for v in (1.0, -0.7, 0.4)]
+        gs = [1.0] * steps
+    dt = 0.5 / n
+    runs = []
+    for mode in ("advance", "calls"):
+        e = E.Ebit(n, "fp64", dev())
+        e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+        C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+        if mode == "advance":
+            e.advance(U, gs, dt, C)
+        else:
+            for g in gs:
+                e.step(U, g, dt)
+                e.front2vof(C)
+        torch.cuda.synchronize()
+        fl, s = e.state()
+        runs.append((fl.cpu().numpy(), [x.cpu().numpy() for x in s], C.cpu().numpy(), e.stats(C)))
+    (f0, s0, c0, st0), (f1, s1, c1, st1) = runs
+    bad = np.argwhere(f0 != f1)
+    assert len(bad) == 0, f"{len(bad)} flag differences, first at {bad[:3].tolist()}"
+    for k in range(3):
+        assert np.array_equal(s0[k], s1[k]), k
+    assert np.array_equal(c0, c1)
+    for key in ("n_interfacial", "n_interfacial_sum", "n_fallback", "n_cfl", "volume", "volume_comp"):
+        assert st0[key] == st1[key], key
