@@ -152,7 +152,8 @@ int ebit_current(const ebit_ctx *ctx);
  * default), the Front2VOF of step k < nsteps - 1 runs in one launch with the
  * x sweep of step k + 1 -- with a surrogate set, its classify pass, the
  * network's pass following that launch (same results; C is complete when
- * the enqueued work ends).
+ * the enqueued work ends).  Within the call each sweep knows the axis of the
+ * next one and passes on a narrower band of bricks (again the same results).
  *   U       3 device pointers: U_x, U_y, U_z (n^3 each, the precision's type)
  *   g       host array of nsteps time factors
  * Returns the first error of the calls it makes (the steps before it are
