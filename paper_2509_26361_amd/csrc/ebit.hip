@@ -962,10 +962,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // that the next sweep copies it into the other buffer
             const bool self = !hasm && !same;
             // the neighbours the next sweep can change from this brick's
-            // markers: along its axis D' nodes -2..+1 from a marker's node,
-            // across it -1..0 (landing edges, crossed nodes, the edges across
-            // whose end colours change, the face colours that read the
-            // segments of three faces); unknown next axis: all 26
+            // markers: along its axis D' nodes -1..+1 from a marker along D'
+            // (landing edges, crossed nodes) and -2..+1 from one across it
+            // (face colours read the segments of three faces); across D'
+            // rows -1..0 from a marker along D' (the edges across whose end
+            // colours change, faces with it on their upper edge) and the
+            // marker's own row otherwise; unknown next axis: all 26
             uint32_t m27 = 0x7ffffffu;
             if (hasm && a.nd >= 0) {
                 // lanes whose node has local coordinate 0, <= 1, 3 along axis e
@@ -975,12 +977,17 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 constexpr unsigned long long k3[3] = {0x8888888888888888ull, 0xF000F000F000F000ull,
                                                       0xFFFF000000000000ull};
                 const int Dn = a.nd, An = (Dn + 1) % 3, Bn = (Dn + 2) % 3;
-                const unsigned long long mb = __ballot((out & 0x70) != 0);
-                // allowed offsets per axis: bit 0 -1, bit 1 0, bit 2 +1
+                // markers on edges along D' / across it
+                const unsigned long long mD = __ballot(((out >> (4 + Dn)) & 1) != 0);
+                const unsigned long long mX = __ballot((out & 0x70 & ~(0x10 << Dn)) != 0);
+                // allowed offsets per axis: bit 0 -1, bit 1 0, bit 2 +1.  Along
+                // D' a marker along D' reaches -1..+1, one across it -2..+1 (the
+                // face colours); across D' only markers along D' reach a row
+                // below (-1)
                 int al[3];
-                al[Dn] = 2 | ((mb & k1[Dn]) != 0 ? 1 : 0) | ((mb & k3[Dn]) != 0 ? 4 : 0);
-                al[An] = 2 | ((mb & k0[An]) != 0 ? 1 : 0);
-                al[Bn] = 2 | ((mb & k0[Bn]) != 0 ? 1 : 0);
+                al[Dn] = 2 | (((mD & k0[Dn]) | (mX & k1[Dn])) != 0 ? 1 : 0) | (((mD | mX) & k3[Dn]) != 0 ? 4 : 0);
+                al[An] = 2 | ((mD & k0[An]) != 0 ? 1 : 0);
+                al[Bn] = 2 | ((mD & k0[Bn]) != 0 ? 1 : 0);
                 m27 = 0;
                 for (int d = 0; d < 27; ++d)
                     if (((al[0] >> (d % 3)) & (al[1] >> (d / 3 % 3)) & (al[2] >> (d / 9))) & 1) m27 |= 1u << d;

@@ -388,7 +388,7 @@ def test_brick_ordered_lists_give_same_results(prec, n):
             assert st0[key] == st1[key], key
 
 
-@pytest.mark.parametrize("case", ["random48", "deformation40", "translation36"])
+@pytest.mark.parametrize("case", ["random48", "deformation40", "translation36", "spheres64"])
 def test_advance_directional_band_equals_single_calls(case):
     """Inside ebit_advance the next sweep's axis is known, and a brick with
     markers adds to the next band only the neighbours that sweep can change
@@ -406,10 +406,17 @@ def test_advance_directional_band_equals_single_calls(case):
         sh = I.sphere_shape(n, centre=(0.35, 0.35, 0.35), R=0.15)
         U = [T(u) for u in I.deformation_velocity(n)]
         gs = [I.deformation_time_factor(k * 0.5 / n, 3.0) for k in range(steps)]
-    else:
+    elif case == "translation36":
         n, steps = 36, 40
         sh = I.sphere_shape(n, centre=(0.3, 0.45, 0.6), R=0.2)
         U = [T(np.full((n, n, n), v)) for v in (1.0, -0.7, 0.4)]
+        gs = [1.0] * steps
+    else:
+        # the large mixed workload in small: many small spheres, random field
+        n, steps = 64, 80
+        cs, rs = I.random_nonoverlapping_spheres(60, 2.0, 6.0, n, gap_cells=2.0, seed=4)
+        sh = I.spheres_shape(n, cs, rs, with_s=False)
+        U = [T(u) for u in I.fourier_velocity(n, seed=5)]
         gs = [1.0] * steps
     dt = 0.5 / n
     runs = []
