@@ -253,10 +253,11 @@ __device__ __forceinline__ void list_put(const ClaimList &L, uint32_t q, uint32_
 // Claims: for each brick of srcA its 27-neighbourhood, restricted by its
 // mask (NULL: none; bit d: the neighbour at offset (d % 3, d / 3 % 3, d / 9)
 // - 1 is claimed), into list A; the bricks of srcS themselves into A; for
-// each brick of srcB the 8 bricks at offsets in {-1, 0}^3 into list B.
+// each brick of srcB the bricks at offsets -(d & 1, d >> 1 & 1, d >> 2) for
+// the bits d of its mask (NULL: all 8) into list B.
 __device__ __forceinline__ void claim_two(const uint32_t *srcA, const uint32_t *maskA, int na, const uint32_t *srcS,
-                                          int ns, const uint32_t *srcB, int nbr, int nb1, ClaimList A, ClaimList B,
-                                          int sub, uint32_t scap, uint32_t ocap)
+                                          int ns, const uint32_t *srcB, const uint8_t *maskB, int nbr, int nb1,
+                                          ClaimList A, ClaimList B, int sub, uint32_t scap, uint32_t ocap)
 {
     const int lane = threadIdx.x & 63;
     const int ta = na * 27 + ns, total = ta + nbr * 8;
@@ -280,6 +281,7 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, const uint32_t *
             } else if (c < total) {
                 const uint32_t b = srcB[(c - ta) >> 3];
                 const int d = (c - ta) & 7;
+                if (maskB && !((maskB[(c - ta) >> 3] >> d) & 1)) use[u] = false;
                 nbk[u] = brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
             }
         }
@@ -450,8 +452,8 @@ __global__ __launch_bounds__(64) void k_init_band(Geo g, const uint8_t *__restri
         if (hasm) {
             const ClaimList A{w.cm, 2u, w.blist[2], w.bnum + 2 * kNum * kPad};
             const uint32_t bp = bpack(bx, by, bz);
-            claim_two(&bp, nullptr, 1, nullptr, 0, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub, (uint32_t)g.scap,
-                      (uint32_t)g.nb);
+            claim_two(&bp, nullptr, 1, nullptr, 0, nullptr, nullptr, 0, g.nb1, A, A, blockIdx.x % kSub,
+                      (uint32_t)g.scap, (uint32_t)g.nb);
         }
     }
 }
@@ -645,6 +647,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     __shared__ uint32_t sq[kSlotCap], sb[kSlotCap];
     __shared__ uint32_t mbr[kClaimCap], cbr[kClaimCap], sbr[kClaimCap];
     __shared__ uint32_t mmk[kClaimCap];
+    __shared__ uint8_t cmk[kClaimCap];
     __shared__ uint32_t ipre[kSub];
     const int lane = threadIdx.x;
     const int n = a.g.n, nb1 = a.g.nb1, nb = a.g.nb;
@@ -692,7 +695,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
     auto claims = [&]() {
         __syncthreads();
-        claim_two(mbr, mmk, nm, sbr, ns, cbr, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
+        claim_two(mbr, mmk, nm, sbr, ns, cbr, cmk, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
                   ClaimList{a.w.fmark, a.fgen, lrev, nrev}, sub, (uint32_t)a.g.scap, (uint32_t)nb);
         __syncthreads();
         nm = 0;
@@ -992,10 +995,23 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 for (int d = 0; d < 27; ++d)
                     if (((al[0] >> (d % 3)) & (al[1] >> (d / 3 % 3)) & (al[2] >> (d / 9))) & 1) m27 |= 1u << d;
             }
+            // Front2VOF: a cell of a lower neighbour reads this brick's nodes
+            // of coordinate 0 along the axes it is lower along; the neighbour
+            // at -1 along axis e needs a revisit only if such a node holds a
+            // marker or changed
+            uint32_t fm8 = 0xffu;
+            if (hasm || chg) {
+                constexpr unsigned long long z0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
+                const unsigned long long rel = __ballot((out & 0x70) != 0 || ((out ^ fself) & 0x71) != 0);
+                const int lx = (rel & z0[0]) != 0, ly = (rel & z0[1]) != 0, lz = (rel & z0[2]) != 0;
+                fm8 = 0;
+                for (int d = 0; d < 8; ++d)
+                    if ((!(d & 1) || lx) && (!(d & 2) || ly) && (!(d & 4) || lz)) fm8 |= 1u << d;
+            }
             if (lane == 0) {
                 if (hasm) { mbr[nm] = (uint32_t)b; mmk[nm] = m27; }
                 if (self) sbr[ns] = (uint32_t)b;
-                if (hasm || chg) cbr[nc] = (uint32_t)b;
+                if (hasm || chg) { cbr[nc] = (uint32_t)b; cmk[nc] = (uint8_t)fm8; }
             }
             nm += hasm ? 1 : 0;
             ns += self ? 1 : 0;
