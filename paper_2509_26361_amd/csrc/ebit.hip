@@ -918,8 +918,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 if (!task[3]) out |= (uint8_t)(c00 << (1 + A1));
             }
             const bool fnode = task[2] || task[3];
-            const bool hasm = __ballot((out & 0x70) != 0) != 0;
-            const bool chg = __ballot(((out ^ fself) & 0x71) != 0) != 0;
+            const unsigned long long mbal = __ballot((out & 0x70) != 0);           // nodes with markers
+            const unsigned long long cbal = __ballot(((out ^ fself) & 0x71) != 0); // colour / marker changed
+            const bool hasm = mbal != 0, chg = cbal != 0;
             // unchanged by this sweep: no marker and no face task in the brick,
             // flags as before (its fractions are 0 then, before and after);
             // bchg records the last sweep that changed the brick
@@ -1002,7 +1003,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             uint32_t fm8 = 0xffu;
             if (hasm || chg) {
                 constexpr unsigned long long z0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
-                const unsigned long long rel = __ballot((out & 0x70) != 0 || ((out ^ fself) & 0x71) != 0);
+                const unsigned long long rel = mbal | cbal;
                 const int lx = (rel & z0[0]) != 0, ly = (rel & z0[1]) != 0, lz = (rel & z0[2]) != 0;
                 fm8 = 0;
                 for (int d = 0; d < 8; ++d)
