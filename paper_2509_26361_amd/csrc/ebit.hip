@@ -88,10 +88,15 @@ constexpr int kSurrWaves = EBIT_SURR_WAVES;   // waves per block of the surrogat
 #ifndef EBIT_SURR_BLOCKS
 #define EBIT_SURR_BLOCKS 256   // one block (weights and tiles in 124 KB of LDS) per CU, each looping over segments
 #endif
+// sweep: bricks staged together -- two on brick-ordered lists (large
+// grids, many bricks per wave), one on claim-ordered lists (a few bricks per
+// wave, where a second brick in the batch only lengthens the first's round)
 #ifndef EBIT_BATCH
 #define EBIT_BATCH 2
 #endif
-constexpr int kBatch = EBIT_BATCH;   // sweep: bricks staged together
+#ifndef EBIT_BATCH_SMALL
+#define EBIT_BATCH_SMALL 1
+#endif
 
 // totals reduced from the per-wave counters
 enum {
@@ -639,6 +644,7 @@ template <typename T, int D, int RUN>
 __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, const int nw)
 {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    constexpr int kBatch = RUN ? EBIT_BATCH : EBIT_BATCH_SMALL;
     __shared__ uint8_t tfl[kBatch][kATile];
     __shared__ double txd[kBatch][kATile];
     __shared__ uint32_t tq[kTaskCap];
