@@ -978,14 +978,13 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // rows -1..0 from a marker along D' (the edges across whose end
             // colours change, faces with it on their upper edge) and the
             // marker's own row otherwise; unknown next axis: all 26
+            // lanes whose node has local coordinate 0, <= 1, 3 along axis e
+            // (lane = x + 4 y + 16 z)
+            constexpr unsigned long long k0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
+            constexpr unsigned long long k1[3] = {0x3333333333333333ull, 0x00FF00FF00FF00FFull, 0xFFFFFFFFull};
+            constexpr unsigned long long k3[3] = {0x8888888888888888ull, 0xF000F000F000F000ull, 0xFFFF000000000000ull};
             uint32_t m27 = 0x7ffffffu;
             if (hasm && a.nd >= 0) {
-                // lanes whose node has local coordinate 0, <= 1, 3 along axis e
-                // (lane = x + 4 y + 16 z)
-                constexpr unsigned long long k0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
-                constexpr unsigned long long k1[3] = {0x3333333333333333ull, 0x00FF00FF00FF00FFull, 0xFFFFFFFFull};
-                constexpr unsigned long long k3[3] = {0x8888888888888888ull, 0xF000F000F000F000ull,
-                                                      0xFFFF000000000000ull};
                 const int Dn = a.nd, An = (Dn + 1) % 3, Bn = (Dn + 2) % 3;
                 // markers on edges along D' / across it
                 const unsigned long long mD = __ballot(((out >> (4 + Dn)) & 1) != 0);
@@ -1008,9 +1007,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // marker or changed
             uint32_t fm8 = 0xffu;
             if (hasm || chg) {
-                constexpr unsigned long long z0[3] = {0x1111111111111111ull, 0x000F000F000F000Full, 0xFFFFull};
                 const unsigned long long rel = mbal | cbal;
-                const int lx = (rel & z0[0]) != 0, ly = (rel & z0[1]) != 0, lz = (rel & z0[2]) != 0;
+                const int lx = (rel & k0[0]) != 0, ly = (rel & k0[1]) != 0, lz = (rel & k0[2]) != 0;
                 fm8 = 0;
                 for (int d = 0; d < 8; ++d)
                     if ((!(d & 1) || lx) && (!(d & 2) || ly) && (!(d & 4) || lz)) fm8 |= 1u << d;
