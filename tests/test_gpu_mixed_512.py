@@ -6,8 +6,9 @@ sweep).
 
 The oracle cannot take a step of this grid in seconds.  What holds at any
 size is checked instead:
-- the run equals, bit for bit, the same run with lists in claim order (the
-  kernels whose oracle parity the smaller tests establish);
+- the run equals, bit for bit, the same run with lists in claim order and
+  the same steps issued as single calls, whose bands take all neighbours
+  (the kernels whose oracle parity the smaller tests establish);
 - the state is consistent: an edge carries a marker exactly where its end
   colours differ (sec. 2.2), and every fraction lies in [0, 1);
 - the interfacial-cell counter agrees with the flags."""
@@ -44,7 +45,10 @@ def workload():
     return phi, pf, U
 
 
-def run(workload, order, prec="fp64", theta=None):
+def run(workload, order, prec="fp64", theta=None, calls=False):
+    """The run through ebit_advance, or (calls) one call per sweep and per
+    Front2VOF, where no sweep knows the next one's axis (all 26 neighbours
+    join the band)."""
     phi, pf, U = workload
     dtype = torch.float64 if prec == "fp64" else torch.float32
     e = E.Ebit(N, prec, dev())
@@ -55,7 +59,13 @@ def run(workload, order, prec="fp64", theta=None):
         e.set_surrogate(theta)
     C = torch.zeros((N, N, N), dtype=dtype, device=dev())
     e.front2vof(C)
-    e.advance([u.to(dtype) for u in U], [1.0] * STEPS, 0.5 / N, C)
+    Ud = [u.to(dtype) for u in U]
+    if calls:
+        for _ in range(STEPS):
+            e.step(Ud, 1.0, 0.5 / N)
+            e.front2vof(C)
+    else:
+        e.advance(Ud, [1.0] * STEPS, 0.5 / N, C)
     torch.cuda.synchronize()
     return e, C
 
@@ -74,6 +84,15 @@ def test_mixed_512_ordered_run_equals_claim_order_and_is_consistent(workload):
     for key in ("n_interfacial", "n_interfacial_sum", "n_fallback", "n_cfl", "volume", "volume_comp"):
         assert st_a[key] == st_b[key], key
     del b, Cb, fb, sb
+    torch.cuda.empty_cache()
+    # single calls: the band without the next axis known
+    c, Cc = run(workload, None, calls=True)
+    fc, sc = c.state()
+    assert torch.equal(fa, fc)
+    for k in range(3):
+        assert torch.equal(sa[k], sc[k]), k
+    assert torch.equal(Ca, Cc)
+    del c, Cc, fc, sc
     torch.cuda.empty_cache()
 
     # edge markers exactly where the end colours differ (x fastest: tensor dim 2 - e)
