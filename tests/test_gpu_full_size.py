@@ -172,3 +172,37 @@ def test_maximum_grid_unit_courant_shift():
     assert v1["n_cfl"] == 0 and v1["n_fallback"] == 0
     V0, V1 = v0["volume"] + v0["volume_comp"], v1["volume"] + v1["volume_comp"]
     assert abs(V1 - V0) <= 1e-9 * V0
+
+
+def test_full_size_advance_equals_single_calls():
+    """The benchmark's launch configuration (ebit_advance: directional band,
+    fused Front2VOF) against the same 150 steps of the 256^3 deformation run
+    issued as single calls (full-neighbourhood band, separate Front2VOF):
+    state, C and counters bit-identical."""
+    sh = I.sphere_shape(N)
+    U = [T(u) for u in I.deformation_velocity(N)]
+    dt = 0.5 / N
+    gs = [I.deformation_time_factor(k * dt, T_END) for k in range(150)]
+    out = []
+    for mode in ("advance", "calls"):
+        e = E.Ebit(N, "fp64", dev())
+        e.init(T(sh.phi_nodes), [T(f) for f in sh.phi_faces])
+        C = torch.zeros((N, N, N), dtype=torch.float64, device=dev())
+        e.front2vof(C)
+        if mode == "advance":
+            e.advance(U, gs, dt, C)
+        else:
+            for g in gs:
+                e.step(U, g, dt)
+                e.front2vof(C)
+        torch.cuda.synchronize()
+        fl, s = e.state()
+        out.append((fl.clone(), [x.clone() for x in s], C.clone(), e.stats(C)))
+        del e
+    (f0, s0, c0, st0), (f1, s1, c1, st1) = out
+    assert torch.equal(f0, f1)
+    for k in range(3):
+        assert torch.equal(s0[k], s1[k]), k
+    assert torch.equal(c0, c1)
+    for key in ("n_interfacial", "n_interfacial_sum", "n_fallback", "n_cfl", "volume", "volume_comp"):
+        assert st0[key] == st1[key], key
