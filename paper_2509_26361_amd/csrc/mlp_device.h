@@ -78,12 +78,26 @@ __device__ __forceinline__ void pack_w1_slot(MlpImage *img, const float *__restr
     img->W.w1[t] = k < kNIn ? to_bf16(theta[kOW1 + k * kNH + j]) : to_bf16(0.f);
 }
 
-// copy `bytes` (a multiple of 16) from device memory into LDS, whole block
+// copy `bytes` (a multiple of 16) from device memory into LDS, whole block.
+// Each lane issues the loads of up to kCopyBatch rounds before their LDS
+// stores, so the copy waits for memory once per batch instead of once per
+// 16-byte round (a block's copy of the weights image is 6 to 20 rounds).
+constexpr int kCopyBatch = 8;
 __device__ __forceinline__ void copy_to_lds(void *dst, const void *__restrict__ src, int bytes)
 {
     const uint4 *s = (const uint4 *)src;
     uint4 *d = (uint4 *)dst;
-    for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+    const int n = bytes / 16, nt = (int)blockDim.x;
+    // indices past the end are clamped to the last entry: those lanes copy
+    // it once more (the same value), and the loop body has no branch that
+    // would pull each load down to its store
+    for (int i0 = (int)threadIdx.x; i0 < n; i0 += kCopyBatch * nt) {
+        uint4 v[kCopyBatch];
+#pragma unroll
+        for (int r = 0; r < kCopyBatch; ++r) v[r] = s[min(i0 + r * nt, n - 1)];
+#pragma unroll
+        for (int r = 0; r < kCopyBatch; ++r) d[min(i0 + r * nt, n - 1)] = v[r];
+    }
 }
 
 __device__ inline void load_weights(MlpWeights &W, const float *__restrict__ theta)
