@@ -290,12 +290,17 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, const uint32_t *
                 nbk[u] = brick_shift(b, nb1, -(d & 1), -((d >> 1) & 1), -(d >> 2));
             }
         }
+        // the four exchanges are issued before any result is compared, so
+        // that they are in flight together
+        uint32_t old[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (!use[u]) continue;
             const ClaimList &L = inA[u] ? A : B;
-            take[u] = atomicExch(&L.mark[blin(nbk[u], nb1)], L.v) != L.v;
+            old[u] = L.v;
+            if (use[u]) old[u] = atomicExch(&L.mark[blin(nbk[u], nb1)], L.v);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) take[u] = use[u] && old[u] != (inA[u] ? A.v : B.v);
         unsigned long long balA[4], balB[4];
         int cA = 0, cB = 0;
 #pragma unroll
@@ -305,11 +310,11 @@ __device__ __forceinline__ void claim_two(const uint32_t *srcA, const uint32_t *
             cA += __popcll(balA[u]);
             cB += __popcll(balB[u]);
         }
-        uint32_t pA = 0, pB = 0;
-        if (lane == 0 && cA) pA = atomicAdd(&A.num[sub * kPad], (uint32_t)cA);
-        if (lane == 0 && cB) pB = atomicAdd(&B.num[sub * kPad], (uint32_t)cB);
-        pA = __shfl(pA, 0);
-        pB = __shfl(pB, 0);
+        // lane 0 adds to A's counter and lane 1 to B's in one instruction
+        // (one round trip; an add of zero leaves its counter as it is)
+        uint32_t p = 0;
+        if (lane < 2) p = atomicAdd(lane == 0 ? &A.num[sub * kPad] : &B.num[sub * kPad], (uint32_t)(lane == 0 ? cA : cB));
+        uint32_t pA = __shfl(p, 0), pB = __shfl(p, 1);
         const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
