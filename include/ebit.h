@@ -49,7 +49,8 @@ enum {
     EBIT_ESTATE = -3,   /* inconsistent state */
     EBIT_EHIP = -4,     /* a HIP runtime call failed */
     EBIT_ENOSURR = -5,  /* surrogate weights missing */
-    EBIT_ESCRATCH = -6  /* scratch buffer too small */
+    EBIT_ESCRATCH = -6, /* scratch buffer too small */
+    EBIT_ETOOBIG = -7   /* input larger than a fixed work space allows */
 };
 
 enum { EBIT_FP64 = 0, EBIT_FP32 = 1 };
@@ -227,6 +228,27 @@ int ebit_mlp_forward(const float *theta, const void *x_bf16, int64_t m, float *y
  * (deterministic).  scratch: device, >= ebit_mlp_scratch_bytes(). */
 int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad, float *loss,
                       void *scratch, size_t scratch_bytes, void *stream);
+
+/* Rows per call of ebit_mlp_gradient_static. */
+#define EBIT_MLP_STATIC_MAX_ROWS 8192
+
+/* ebit_mlp_gradient for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, as ebit_mlp_gradient on
+ * the same rows, with the work space in a static device array of the library
+ * (about 10 MB per GPU, held until the process ends) instead of a caller
+ * buffer.  theta, x_bf16, c, grad, loss as for ebit_mlp_gradient.
+ *   m       1 .. EBIT_MLP_STATIC_MAX_ROWS rows; larger m returns EBIT_ETOOBIG
+ *           (nothing is enqueued)
+ * Allocates nothing: no hipMalloc / hipFree, no library call that allocates.
+ * The first call on a device looks up that device's copy of the array.  Every
+ * call on one GPU shares that GPU's array, so calls that overlap on one GPU
+ * (other streams, other host threads) race: order them on one stream.
+ * Nothing in the array needs clearing: each call writes every entry it reads.
+ * EBIT_EINVAL for null pointers or m <= 0; EBIT_EHIP if the device or the
+ * array's address cannot be obtained. */
+int ebit_mlp_gradient_static(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad,
+                             float *loss, void *stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
  * on theta with first / second moments m1, m2 (float32, param_count each). */

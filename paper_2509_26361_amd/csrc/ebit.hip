@@ -2079,6 +2079,7 @@ const char *ebit_strerror(int code)
     case EBIT_EHIP: return "HIP runtime error";
     case EBIT_ENOSURR: return "surrogate weights missing";
     case EBIT_ESCRATCH: return "scratch buffer too small";
+    case EBIT_ETOOBIG: return "input larger than the fixed work space allows";
     default: return "unknown error";
     }
 }

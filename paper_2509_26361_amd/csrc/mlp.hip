@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/ebit.h"
 #include "mlp_device.h"
 
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float *__restrict
 constexpr int kGradBlocks = 256;
 constexpr size_t kPartialBytes = (size_t)kGradBlocks * kPartial * sizeof(float);   // a multiple of 16
 
-inline MlpImage *image_of(void *scratch) { return (MlpImage *)((char *)scratch + kPartialBytes); }
+inline MlpImage *image_of(void *work) { return (MlpImage *)((char *)work + kPartialBytes); }
 
 inline int grad_blocks(long m)
 {
@@ -397,11 +399,66 @@ inline AdamStep adam_step(int64_t t, float lr)
     return AdamStep{lr, (float)(1.0 - pow(0.9, (double)t)), (float)(1.0 - pow(0.999, (double)t))};
 }
 
-// scratch: partial sums, then the parameters' image (16-byte aligned)
-inline int scratch_ok(const void *scratch, size_t bytes)
+// work space: partial sums, then the parameters' image (16-byte aligned)
+inline int scratch_ok(const void *work, size_t bytes)
 {
-    if (!scratch || ((uintptr_t)scratch & 15)) return EBIT_EINVAL;
+    if (!work || ((uintptr_t)work & 15)) return EBIT_EINVAL;
     return bytes < kPartialBytes + sizeof(MlpImage) ? EBIT_ESCRATCH : EBIT_OK;
+}
+
+// gradient of the mean squared error over m rows: the parameters' image,
+// per-workgroup partial sums (grad_blocks(m) of them, kPartial floats
+// apart, from `partial`), their fixed-order sum
+int launch_gradient(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad, float *loss,
+                    float *partial, MlpImage *img, hipStream_t st)
+{
+    const int blocks = grad_blocks(m);
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kPackThreads + 255) / 256), dim3(256), 0, st, theta, img);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, img, (const uint16_t *)x_bf16, c,
+                       (const int64_t *)nullptr, (long)m, (long)m, partial);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)partial, blocks,
+                       (long)m, grad, loss);
+    return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
+}
+
+// --------------------------------------------------------------------------
+// the gradient's work space in a static device array, for callers that
+// cannot allocate (ebit_mlp_gradient_static): the partial sums of
+// grad_blocks(EBIT_MLP_STATIC_MAX_ROWS) workgroups, then the image.  Every
+// GPU holds its own copy at its own address; host code uses only the address
+// hipGetSymbolAddress returns for the current device, never the array's name.
+// --------------------------------------------------------------------------
+
+constexpr int kStaticBlocks = (EBIT_MLP_STATIC_MAX_ROWS + 63) / 64;
+static_assert(kStaticBlocks <= kGradBlocks, "static work space larger than the allocating path's");
+constexpr size_t kStaticPartialBytes = ((size_t)kStaticBlocks * kPartial * sizeof(float) + 255) / 256 * 256;
+constexpr size_t kStaticBytes = kStaticPartialBytes + sizeof(MlpImage);
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_addr[kMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticBytes];
+
+namespace {
+
+// address of the current device's copy of the static array (looked up once
+// per device, with that device current)
+int static_scratch(char **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return EBIT_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return EBIT_EHIP;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EBIT_EHIP;
+        g_static_addr[dev] = (char *)p;
+    }
+    *out = g_static_addr[dev];
+    return EBIT_OK;
 }
 
 }  // namespace
@@ -425,19 +482,22 @@ int ebit_mlp_forward(const float *theta, const void *x_bf16, int64_t m, float *y
 }
 
 int ebit_mlp_gradient(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad, float *loss,
-                      void *scratch, size_t scratch_bytes, void *stream)
+                      void *work, size_t work_bytes, void *stream)
 {
     if (!theta || !x_bf16 || !c || !grad || m <= 0) return EBIT_EINVAL;
-    if (int e = scratch_ok(scratch, scratch_bytes)) return e;
-    const int blocks = grad_blocks(m);
-    hipStream_t st = (hipStream_t)stream;
-    MlpImage *img = image_of(scratch);
-    hipLaunchKernelGGL(k_mlp_pack, dim3((kPackThreads + 255) / 256), dim3(256), 0, st, theta, img);
-    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, img, (const uint16_t *)x_bf16, c,
-                       (const int64_t *)nullptr, (long)m, (long)m, (float *)scratch);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)scratch, blocks,
-                       (long)m, grad, loss);
-    return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
+    if (int e = scratch_ok(work, work_bytes)) return e;
+    return launch_gradient(theta, x_bf16, c, m, grad, loss, (float *)work, image_of(work), (hipStream_t)stream);
+}
+
+int ebit_mlp_gradient_static(const float *theta, const void *x_bf16, const float *c, int64_t m, float *grad,
+                             float *loss, void *stream)
+{
+    if (!theta || !x_bf16 || !c || !grad || m <= 0) return EBIT_EINVAL;
+    if (m > EBIT_MLP_STATIC_MAX_ROWS) return EBIT_ETOOBIG;
+    char *base = nullptr;
+    if (int e = static_scratch(&base)) return e;
+    return launch_gradient(theta, x_bf16, c, m, grad, loss, (float *)base,
+                           (MlpImage *)(base + kStaticPartialBytes), (hipStream_t)stream);
 }
 
 int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t step, float lr, void *stream)
@@ -450,22 +510,22 @@ int ebit_mlp_adam(float *theta, float *m1, float *m2, const float *grad, int64_t
 
 int ebit_mlp_train(float *theta, float *m1, float *m2, const void *x_bf16, const float *c, int64_t nrows,
                    const int64_t *idx, int64_t batch, int64_t steps, const float *lr, int64_t step0, float *losses,
-                   void *scratch, size_t scratch_bytes, void *stream)
+                   void *work, size_t work_bytes, void *stream)
 {
     if (!theta || !m1 || !m2 || !x_bf16 || !c || nrows <= 0 || batch <= 0 || steps < 0 || step0 < 0) return EBIT_EINVAL;
     if (steps > 0 && !lr) return EBIT_EINVAL;
     if (!idx && batch > nrows) return EBIT_EINVAL;
-    if (int e = scratch_ok(scratch, scratch_bytes)) return e;
+    if (int e = scratch_ok(work, work_bytes)) return e;
     if (steps == 0) return EBIT_OK;
     const int blocks = grad_blocks(batch);
     hipStream_t st = (hipStream_t)stream;
-    MlpImage *img = image_of(scratch);
+    MlpImage *img = image_of(work);
     hipLaunchKernelGGL(k_mlp_pack, dim3((kPackThreads + 255) / 256), dim3(256), 0, st, theta, img);
     for (int64_t s = 0; s < steps; ++s) {
         hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, img, (const uint16_t *)x_bf16, c,
                            idx ? idx + s * batch : (const int64_t *)nullptr, (long)nrows, (long)batch,
-                           (float *)scratch);
-        hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)scratch,
+                           (float *)work);
+        hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kPartial + 63) / 64), dim3(256), 0, st, (const float *)work,
                            blocks, (long)batch, losses ? losses + s : (float *)nullptr, theta, m1, m2, img,
                            adam_step(step0 + s + 1, lr[s]));
         if ((s & 255) == 255 && hipGetLastError() != hipSuccess) return EBIT_EHIP;

@@ -15,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebit.so")
 
 EBIT_OK, EBIT_EINVAL, EBIT_ECFL, EBIT_ESTATE, EBIT_EHIP, EBIT_ENOSURR, EBIT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+EBIT_ETOOBIG = -7
+EBIT_MLP_STATIC_MAX_ROWS = 8192
 EBIT_FP64, EBIT_FP32 = 0, 1
 EBIT_OPT_FULL_GRID, EBIT_OPT_TIMING, EBIT_OPT_FUSE, EBIT_OPT_SUBLIST_CAP, EBIT_OPT_ORDER = 1, 2, 3, 4, 5
 
@@ -101,6 +103,8 @@ def lib():
         L.ebit_mlp_forward.restype = ctypes.c_int
         L.ebit_mlp_gradient.argtypes = [P, P, P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]
         L.ebit_mlp_gradient.restype = ctypes.c_int
+        L.ebit_mlp_gradient_static.argtypes = [P, P, P, ctypes.c_int64, P, P, P]
+        L.ebit_mlp_gradient_static.restype = ctypes.c_int
         L.ebit_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_float, P]
         L.ebit_mlp_adam.restype = ctypes.c_int
         L.ebit_mlp_train.argtypes = [P, P, P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, P,
@@ -302,6 +306,15 @@ def mlp_forward(theta, x_bf16, y=None, stream=None):
         y = torch.empty(m, dtype=torch.float32, device=x_bf16.device)
     _check(lib().ebit_mlp_forward(_ptr(theta), _ptr(x_bf16), m, _ptr(y), _stream(stream)), "ebit_mlp_forward")
     return y
+
+
+def mlp_gradient_static(theta, x_bf16, c, grad, loss=None, stream=None):
+    """ebit_mlp_gradient_static: the gradient into `grad` (and the loss into
+    `loss`) with the library's static work space (at most
+    EBIT_MLP_STATIC_MAX_ROWS rows, no allocation by the library)."""
+    _check(lib().ebit_mlp_gradient_static(_ptr(theta), _ptr(x_bf16), _ptr(c), x_bf16.shape[0], _ptr(grad),
+                                          _ptr(loss), _stream(stream)), "ebit_mlp_gradient_static")
+    return grad, loss
 
 
 class MlpTrainer:

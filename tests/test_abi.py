@@ -98,3 +98,15 @@ def test_mlp_entry_points_reject_bad_arguments_on_host(lib):
     assert L.ebit_mlp_gradient(ok, ok, ok, 10, ok, None, ok, need - 16, None) == E.EBIT_ESCRATCH
     assert L.ebit_mlp_gradient(ok, ok, ok, 0, ok, None, ok, need, None) == E.EBIT_EINVAL
     assert L.ebit_mlp_adam(ok, ok, ok, ok, 0, 1e-3, None) == E.EBIT_EINVAL
+
+
+def test_static_gradient_rejects_bad_arguments_on_host(lib):
+    """ebit_mlp_gradient_static checks its arguments before it looks up its
+    static work space or enqueues anything."""
+    from paper_2509_26361_amd import ebit as E
+    L = E.lib()
+    ok = ctypes.c_void_p(4096)
+    assert L.ebit_mlp_gradient_static(ok, ok, ok, 0, ok, None, None) == E.EBIT_EINVAL
+    assert L.ebit_mlp_gradient_static(None, ok, ok, 10, ok, None, None) == E.EBIT_EINVAL
+    assert L.ebit_mlp_gradient_static(ok, ok, ok, E.EBIT_MLP_STATIC_MAX_ROWS + 1, ok, None, None) == E.EBIT_ETOOBIG
+    assert L.ebit_strerror(E.EBIT_ETOOBIG).decode().startswith("input larger")
