@@ -34,31 +34,52 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def build_variant(source: str, workdir: str):
+    """Compile oracle source text (e.g. a copy with a deliberately planted
+    mistake, for tests that show a pin detects it) into ``workdir`` and return
+    the loaded library; the oracle itself is not touched."""
+    src = os.path.join(workdir, "variant.c")
+    so = os.path.join(workdir, "libvariant.so")
+    with open(src, "w") as f:
+        f.write(source)
+    subprocess.check_call(["gcc", *CFLAGS, "-o", so, src, "-lm"])
+    return _declare(ctypes.CDLL(so))
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_SO)
-        P = ctypes.c_void_p
-        L.orc_init.argtypes = [ctypes.c_int] + [P] * 11
-        L.orc_init.restype = ctypes.c_int
-        L.orc_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                P, P, P, P, P, P, P, P, P, P]
-        L.orc_sweep.restype = ctypes.c_int
-        L.orc_f2v.argtypes = [ctypes.c_int, P, P, P, P, P, P]
-        L.orc_f2v.restype = None
-        L.orc_volume.argtypes = [ctypes.c_long, P, P]
-        L.orc_volume.restype = ctypes.c_double
-        L.orc_count_interfacial.argtypes = [ctypes.c_int, P]
-        L.orc_count_interfacial.restype = ctypes.c_long
-        L.orc_fit_height.argtypes = [P, P]
-        L.orc_fit_height.restype = ctypes.c_double
-        L.orc_cell_loops.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, P, P, P]
-        L.orc_cell_loops.restype = ctypes.c_int
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_SO))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the exported functions."""
+    P = ctypes.c_void_p
+    L.orc_init.argtypes = [ctypes.c_int] + [P] * 11
+    L.orc_init.restype = ctypes.c_int
+    L.orc_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                            P, P, P, P, P, P, P, P, P, P]
+    L.orc_sweep.restype = ctypes.c_int
+    L.orc_f2v.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+    L.orc_f2v.restype = None
+    L.orc_volume.argtypes = [ctypes.c_long, P, P]
+    L.orc_volume.restype = ctypes.c_double
+    L.orc_count_interfacial.argtypes = [ctypes.c_int, P]
+    L.orc_count_interfacial.restype = ctypes.c_long
+    L.orc_fit_height.argtypes = [P, P]
+    L.orc_fit_height.restype = ctypes.c_double
+    L.orc_cell_loops.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, P, P, P]
+    L.orc_cell_loops.restype = ctypes.c_int
+    return L
 
 
 def _p(a):
@@ -96,14 +117,15 @@ def init(shape, exact: bool = False) -> State:
     return State(n, flags, s)
 
 
-def sweep(st: State, d: int, g: float, dt: float, U) -> tuple:
+def sweep(st: State, d: int, g: float, dt: float, U, L=None) -> tuple:
     """One advection sweep along axis ``d`` (0, 1, 2); returns (new state,
-    counters[fallback, multi-crossing, cfl, aligned-merges])."""
+    counters[fallback, multi-crossing, cfl, aligned-merges]).  ``L``: a
+    library from build_variant instead of the oracle."""
     n = st.n
     U = _f64(U)
     out = State(n, np.zeros_like(st.flags), [np.zeros_like(x) for x in st.s])
     cnt = np.zeros(4, np.int64)
-    lib().orc_sweep(n, int(d), float(g), float(dt), _p(U), _p(st.flags),
+    (L or lib()).orc_sweep(n, int(d), float(g), float(dt), _p(U), _p(st.flags),
                     _p(st.s[0]), _p(st.s[1]), _p(st.s[2]), _p(out.flags),
                     _p(out.s[0]), _p(out.s[1]), _p(out.s[2]), _p(cnt))
     return out, cnt
