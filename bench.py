@@ -74,9 +74,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=16)
-    p.add_argument("--workload", default="deformation", choices=["deformation", "mixed"],
+    p.add_argument("--workload", default="deformation", choices=["deformation", "mixed", "tables"],
                    help="deformation: the 256^3 deformation test (the default line); mixed: 512^3, 4096 random "
-                        "spheres in a random divergence-free field, 100 steps")
+                        "spheres in a random divergence-free field, 100 steps; tables: the paper's convergence "
+                        "studies (translation and deformation, N = 32..256, CFL 0.125) with their errors")
     p.add_argument("--n", type=int, default=256)
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -181,6 +182,8 @@ def main():
     from paper_2509_26361_amd import inputs as I
     if a.workload == "mixed":
         return run_mixed(a, E, I, torch)
+    if a.workload == "tables":
+        return run_tables(a, E, I, torch)
 
     n = a.n
     dt = 0.5 / n
@@ -438,6 +441,69 @@ def run_mixed(a, E, I, torch):
             out[name]["training"] = surr[1]
         del q
         torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+# the paper's mesh-convergence studies (sec. 3.1.2 Table 2, sec. 3.2 Table 3)
+PAPER_TABLES = {
+    "translation": {"N": [32, 64, 128, 256], "E_mass": [5.03e-4, 6.13e-5, 1.35e-5, 2.81e-6],
+                    "E_shape": [1.56e-3, 3.68e-4, 1.25e-4, 2.95e-5]},
+    "deformation": {"N": [32, 64, 128, 256], "E_mass": [3.06e-1, 9.78e-2, 3.22e-3, 1.49e-3],
+                    "E_shape": [5.66e-1, 2.23e-1, 3.82e-2, 1.58e-2]},
+}
+
+
+def table_case(E, I, torch, case, n, precision="fp64"):
+    """One convergence run on the GPU: translation (sphere R = 0.15 at 0.25,
+    u = (1,1,1) reversed at T/2, T = 1) or deformation (sphere at 0.35,
+    LeVeque's field x cos(pi t/3), T = 3), CFL 0.125; E_mass from the volume
+    after every step, E_shape at T (ebit_errors)."""
+    dev = torch.device("cuda:0")
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    tdev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev).to(dtype)
+    if case == "translation":
+        sh, U, T = I.sphere_shape(n, centre=(0.25, 0.25, 0.25)), I.uniform_velocity(n), 1.0
+    else:
+        sh, U, T = I.sphere_shape(n), I.deformation_velocity(n), 3.0
+    dt = 0.125 / n
+    steps = int(round(T / dt))
+    e = E.Ebit(n, precision, dev)
+    e.init(tdev(sh.phi_nodes).double(), [tdev(f).double() for f in sh.phi_faces])
+    Ud = [tdev(u) for u in U]
+    C0 = torch.zeros((n, n, n), dtype=dtype, device=dev)
+    e.front2vof(C0)
+    C = torch.zeros_like(C0)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if case == "translation":
+            g = 1.0 if k < steps // 2 else -1.0
+        else:
+            g = I.deformation_time_factor(k * dt, T)
+        e.advance(Ud, [g], dt, C)
+        r = e.errors(C, C0, reset=(k == 0))
+    wall = time.perf_counter() - t0
+    st = e.stats(C)
+    return {"N": n, "steps": steps, "E_mass": r["e_mass"], "E_shape": r["e_shape"],
+            "volume_change_at_T": (r["volume"] - r["volume_ref"]) / r["volume_ref"],
+            "max_courant": st["max_courant"], "n_merged": st["n_merged"], "n_multi": st["n_multi"],
+            "n_fallback": st["n_fallback"], "wall_s": wall}
+
+
+def run_tables(a, E, I, torch):
+    """Both convergence studies at N = 32, 64, 128, 256 against the paper's
+    printed errors (context: the same algorithm's readings, not a target)."""
+    out = {"workload": "paper convergence studies, CFL 0.125, FP64", "precision": a.precision, "cases": {}}
+    for case in ("translation", "deformation"):
+        rows = []
+        for n, pm, ps in zip(PAPER_TABLES[case]["N"], PAPER_TABLES[case]["E_mass"], PAPER_TABLES[case]["E_shape"]):
+            r = table_case(E, I, torch, case, n, a.precision)
+            r["paper_E_mass"], r["paper_E_shape"] = pm, ps
+            r["ratio_E_mass"], r["ratio_E_shape"] = r["E_mass"] / pm, r["E_shape"] / ps
+            print(f"[bench] {case} N={n}: E_mass {r['E_mass']:.3e} (paper {pm:.2e}), "
+                  f"E_shape {r['E_shape']:.3e} (paper {ps:.2e}), {r['wall_s']:.1f} s", file=sys.stderr, flush=True)
+            rows.append(r)
+            torch.cuda.empty_cache()
+        out["cases"][case] = rows
     print(json.dumps(out), flush=True)
 
 

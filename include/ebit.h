@@ -133,6 +133,8 @@ typedef struct {
     int64_t n_active_cells; /* sweeps so far: cells processed (work-list sizes) */
     int64_t step_sweeps;    /* sweeps so far */
     int64_t n_interfacial_sum; /* sum of n_interfacial over every ebit_front2vof so far */
+    double max_courant;     /* sweeps so far: largest |(dt n) g u| of a marker, in cells (FP32 precision;
+                               sec. 2.3 requires <= 1) */
 } ebit_stats_t;
 
 /*
@@ -141,6 +143,26 @@ typedef struct {
  * so far broke the Courant limit, else EBIT_OK.
  */
 int ebit_stats(ebit_ctx *ctx, const void *C, ebit_stats_t *out, void *stream);
+
+/* The paper's error measures (sec. 3.1.2, eqs. Eq_error_surface and
+ * Eq_error_shape) of a volume-fraction field C against a reference C0 (the
+ * initial field, or one from another run), both device arrays of n^3 cells in
+ * the context's precision:
+ *   volume, volume_ref   compensated sums of C and of C0 (cell units)
+ *   l1_diff              sum over cells of |C - C0|
+ *   e_shape              l1_diff / volume_ref (Eq_error_shape; meaningful
+ *                        when the interface should be back where C0 has it)
+ *   e_mass               mean of |volume - volume_ref| / volume_ref over the
+ *                        calls since the last one with `reset` set, this one
+ *                        included (Eq_error_surface when called once after
+ *                        every step's ebit_front2vof with the initial C0)
+ * One fixed-order reduction over both arrays (deterministic); synchronises
+ * `stream`. */
+typedef struct {
+    double volume, volume_ref, l1_diff, e_shape, e_mass;
+    int64_t samples;        /* calls in the e_mass mean */
+} ebit_errors_t;
+int ebit_errors(ebit_ctx *ctx, const void *C, const void *C0, int reset, ebit_errors_t *out, void *stream);
 
 /* Index (0 or 1) of the state buffer holding the current state. */
 int ebit_current(const ebit_ctx *ctx);

@@ -101,11 +101,12 @@ constexpr int kSurrWaves = EBIT_SURR_WAVES;   // waves per block of the surrogat
 // totals reduced from the per-wave counters
 enum {
     ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM /* sum of gen * delta */, ST_INTER, ST_AMB,
-    ST_MARK0, ST_MARK1, ST_MARK2, ST_COUNT = 16
+    ST_MARK0, ST_MARK1, ST_MARK2, ST_CMAX /* bits of the largest |Courant number| (float) */, ST_COUNT = 16
 };
 // per-wave counters: cumulative over sweeps / Front2VOF calls, except the
-// last-Front2VOF one (CS_AMB)
-enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_GEN, CS_INTER, CS_AMB, CS_COUNT };
+// last-Front2VOF one (CS_AMB); CS_CMAX holds the bits of a non-negative float
+// (ordered like the float) and is reduced by maximum
+enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_GEN, CS_INTER, CS_AMB, CS_CMAX, CS_COUNT };
 
 struct Geo {
     int n;
@@ -158,6 +159,7 @@ struct Work {
     long long *doff;     // [nw] their offsets in the output
     unsigned long long *stat;   // ST_* totals
     double *part;        // 2 * kRedBlocks reduction partials
+    double *epart;       // 6 * kRedBlocks partials of the error sums (ebit_errors), then the 6 totals
     ebit_mlp::MlpImage *simg;   // the surrogate's weights in the layout its kernel stages in LDS
     uint32_t *ocnt;      // [kOrderBlocks] band-ordering counts / offsets
 };
@@ -188,6 +190,7 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(nw * 8); if (w) w->doff = (long long *)p;
     p = take(ST_COUNT * sizeof(unsigned long long)); if (w) w->stat = (unsigned long long *)p;
     p = take(2 * kRedBlocks * sizeof(double)); if (w) w->part = (double *)p;
+    p = take(6 * (kRedBlocks + 1) * sizeof(double)); if (w) w->epart = (double *)p;
     p = take(sizeof(ebit_mlp::MlpImage)); if (w) w->simg = (ebit_mlp::MlpImage *)p;
     p = take(kOrderBlocks * 4); if (w) w->ocnt = (uint32_t *)p;
     return off;
@@ -704,6 +707,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     }
     int ntask = 0, nslot = 0, nact = 0, nm = 0, nc = 0, ns = 0;
     int fbc = 0, cflc = 0, mergedc = 0, fbt = 0, multit = 0;
+    float cmax = 0.f;   // largest |displacement| of a marker this wave owns, in cells
     auto claims = [&]() {
         __syncthreads();
         claim_two(mbr, mmk, nm, sbr, ns, cbr, cmk, nc, nb1, ClaimList{cm_next, t + 1, lnext, nnext},
@@ -838,6 +842,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                         xd = (double)sD[j][r] + (double)del;
                         const bool own = kt[D] >= 1 && kt[D] < 5 && kt[A1] < 4 && kt[A2] < 4;
                         if (own && fabs((double)del) > 1.0) ++cfl;
+                        if (own) cmax = fmaxf(cmax, fabsf((float)del));
                     }
                     tfl[j][ti] = fr[j][r];
                     txd[j][ti] = xd;
@@ -849,6 +854,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                     if ((fown[j] >> (4 + A)) & 1) {
                         T del = a.c * (Uown[j] + sAo[j][e] * (UAo[j][e] - Uown[j]));
                         if (fabs((double)del) > 1.0) ++cfl;
+                        cmax = fmaxf(cmax, fabsf((float)del));
                     }
                 }
             }
@@ -1040,6 +1046,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     cflc = wave_sum(cflc);
     mergedc = wave_sum(mergedc);
     multit = wave_sum(multit);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, off));
     // (adds whose result is not waited for)
     if (lane == 0) {
         const int nwv = a.g.nw;
@@ -1048,6 +1056,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
         if (cflc) atomicAdd(&a.w.cs[CS_CFL * nwv + wv], (unsigned long long)cflc);
         if (mergedc) atomicAdd(&a.w.cs[CS_MERGED * nwv + wv], (unsigned long long)mergedc);
         if (nact) atomicAdd(&a.w.cs[CS_ACTIVE * nwv + wv], (unsigned long long)nact * 64ull);
+        if (cmax > 0.f) atomicMax(&a.w.cs[CS_CMAX * nwv + wv], (unsigned long long)__float_as_uint(cmax));
     }
 }
 
@@ -1716,17 +1725,25 @@ __global__ __launch_bounds__(256) void k_stats_reduce(Work w, Geo g)
     unsigned long long acc[CS_COUNT];
     for (int k = 0; k < CS_COUNT; ++k) acc[k] = 0;
     for (int ch = threadIdx.x; ch < g.nw; ch += blockDim.x)
-        for (int k = 0; k < CS_COUNT; ++k) acc[k] += w.cs[k * g.nw + ch];
+        for (int k = 0; k < CS_COUNT; ++k) {
+            const unsigned long long v = w.cs[k * g.nw + ch];
+            acc[k] = k == CS_CMAX ? max(acc[k], v) : acc[k] + v;
+        }
     for (int k = 0; k < CS_COUNT; ++k) {
         unsigned long long v = acc[k];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long u = __shfl_xor(v, off);
+            v = k == CS_CMAX ? max(v, u) : v + u;
+        }
         if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
     }
     __syncthreads();
     if (threadIdx.x < CS_COUNT) {
         const int k = threadIdx.x;
-        unsigned long long v = red[k][0] + red[k][1] + red[k][2] + red[k][3];
-        const int map[CS_COUNT] = {ST_FALLBACK, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB};
+        unsigned long long v = k == CS_CMAX ? max(max(red[k][0], red[k][1]), max(red[k][2], red[k][3]))
+                                            : red[k][0] + red[k][1] + red[k][2] + red[k][3];
+        const int map[CS_COUNT] = {ST_FALLBACK, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB,
+                                   ST_CMAX};
         w.stat[map[k]] = v;
     }
 }
@@ -1800,6 +1817,58 @@ __global__ void k_vol_final(double *part, int nblocks)
     }
 }
 
+// error sums against a reference C0 (secs. 3.1-3.2, eqs. Eq_error_surface and
+// Eq_error_shape): compensated sums of C, of C0 and of |C - C0|, each with the
+// same fixed reduction order as k_vol_partial
+template <typename T>
+__global__ __launch_bounds__(256) void k_err_partial(const T *__restrict__ C, const T *__restrict__ C0, long N,
+                                                     double *__restrict__ part)
+{
+    __shared__ double ss[3][256], sc[3][256];
+    double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
+    long stride = (long)gridDim.x * blockDim.x;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += stride) {
+        const double a = (double)C[q], b = (double)C0[q];
+        neumaier_add(s[0], c[0], a);
+        neumaier_add(s[1], c[1], b);
+        neumaier_add(s[2], c[2], fabs(a - b));
+    }
+    for (int k = 0; k < 3; ++k) {
+        ss[k][threadIdx.x] = s[k];
+        sc[k][threadIdx.x] = c[k];
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int k = 0; k < 3; ++k) {
+                double s1 = ss[k][threadIdx.x], c1 = sc[k][threadIdx.x];
+                neumaier_add(s1, c1, ss[k][threadIdx.x + h]);
+                ss[k][threadIdx.x] = s1;
+                sc[k][threadIdx.x] = c1 + sc[k][threadIdx.x + h];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        part[6 * blockIdx.x + 2 * threadIdx.x] = ss[threadIdx.x][0];
+        part[6 * blockIdx.x + 2 * threadIdx.x + 1] = sc[threadIdx.x][0];
+    }
+}
+
+__global__ void k_err_final(double *part, int nblocks)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        double s = 0.0, c = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            neumaier_add(s, c, part[6 * b + 2 * k]);
+            c += part[6 * b + 2 * k + 1];
+        }
+        part[6 * nblocks + 2 * k] = s;
+        part[6 * nblocks + 2 * k + 1] = c;
+    }
+}
+
 __global__ void k_zero_marks(unsigned long long *stat)
 {
     if (threadIdx.x < 3) stat[ST_MARK0 + threadIdx.x] = 0;
@@ -1833,6 +1902,8 @@ struct ebit_ctx {
     hipEvent_t *ev;        // 2 * kTimed events
     uint8_t *ev_kind;      // 0 sweep, 1 Front2VOF, 2 Front2VOF with the x sweep
     int ev_n;              // launches recorded since the last ebit_timing
+    double mass_sum;       // ebit_errors: sum of |V - V0| / V0 since the last reset
+    int64_t mass_n;        // and the number of calls in it
 };
 
 namespace {
@@ -2214,7 +2285,46 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     // generations 1..K so far: (K + 1) S1 - sum of j delta_j
     const int64_t K = (int64_t)c->fgen - 1;
     out->n_interfacial_sum = (K + 1) * (int64_t)stat[ST_INTER] - (int64_t)stat[ST_INTER_SUM];
+    const uint32_t cbits = (uint32_t)stat[ST_CMAX];
+    float cm;
+    memcpy(&cm, &cbits, sizeof(cm));
+    out->max_courant = (double)cm;
     return out->n_cfl ? EBIT_ECFL : EBIT_OK;
+}
+
+int ebit_errors(ebit_ctx *c, const void *C, const void *C0, int reset, ebit_errors_t *out, void *stream)
+{
+    if (!c || !C || !C0 || !out) return EBIT_EINVAL;
+    hipStream_t st = S(stream);
+    const long N = (long)c->n * c->n * c->n;
+    if (c->precision == EBIT_FP64)
+        hipLaunchKernelGGL(k_err_partial<double>, dim3(kRedBlocks), dim3(256), 0, st, (const double *)C,
+                           (const double *)C0, N, c->w.epart);
+    else
+        hipLaunchKernelGGL(k_err_partial<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float *)C,
+                           (const float *)C0, N, c->w.epart);
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, st, c->w.epart, kRedBlocks);
+    int rc = check_launch();
+    if (rc != EBIT_OK) return rc;
+    double tot[6];
+    if (hipMemcpyAsync(tot, c->w.epart + 6 * kRedBlocks, sizeof(tot), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return EBIT_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return EBIT_EHIP;
+    out->volume = tot[0] + tot[1];
+    out->volume_ref = tot[2] + tot[3];
+    out->l1_diff = tot[4] + tot[5];
+    out->e_shape = out->volume_ref > 0.0 ? out->l1_diff / out->volume_ref : 0.0;
+    if (reset) {
+        c->mass_sum = 0.0;
+        c->mass_n = 0;
+    }
+    if (out->volume_ref > 0.0) {
+        c->mass_sum += fabs(out->volume - out->volume_ref) / out->volume_ref;
+        c->mass_n += 1;
+    }
+    out->samples = c->mass_n;
+    out->e_mass = c->mass_n ? c->mass_sum / (double)c->mass_n : 0.0;
+    return EBIT_OK;
 }
 
 int ebit_current(const ebit_ctx *c) { return c ? c->cur : -1; }

@@ -218,6 +218,9 @@ struct PlaneTask {
         else { Xb = (double)xb + (double)delb; Yb = (double)yb + (double)s_b; }
     }
 
+    // Geometry (advected positions, crossings, circle fits) runs in FP64 in
+    // both precisions; the FP32 form rounds only the velocity interpolation
+    // and the stored result to FP32.
     // The task of one node in this plane (sec. 2.1, 2.3).  Always: the colour
     // at the centre of Q(0,0) relative to the advected polyline -- start from
     // the node's new colour c00, flip for aligned markers landing in [0, 1/2)
@@ -280,7 +283,7 @@ struct PlaneTask {
         for (int f = 0; f < 4; ++f) pk[f] = pairs(f - 2, 0);
         // crossing of segment t of face f with the line X = x0 (from the endpoint left of
         // the line to the one right of it); false if the segment does not cross it
-        auto cross = [&](int f, int t, double x0, T &key) -> bool {
+        auto cross = [&](int f, int t, double x0, double &key) -> bool {
             if (t >= nseg(pk[f])) return false;
             double Ax, Ay, Bx, By;
             pt(f, side_a(pk[f], t), Ax, Ay);
@@ -288,7 +291,7 @@ struct PlaneTask {
             const bool sa = x0 <= Ax, sb = x0 <= Bx;
             if (sa == sb) return false;
             const double Lx = sa ? Bx : Ax, Ly = sa ? By : Ay, Rx = sa ? Ax : Bx, Ry = sa ? Ay : By;
-            key = line_cross<T>((T)x0, (T)Lx, (T)Ly, (T)Rx, (T)Ry);
+            key = line_cross<double>(x0, Lx, Ly, Rx, Ry);
             return true;
         };
         // face-centre colour (faces -1..1)
@@ -303,19 +306,19 @@ struct PlaneTask {
         for (int f = 1; f < 4; ++f)
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                T y;
-                if (cross(f, t, 0.5, y) && y < T(0.5)) par ^= 1;
+                double y;
+                if (cross(f, t, 0.5, y) && y < 0.5) par ^= 1;
             }
         if (!unal) return par;
         // new marker on V(0,0) (faces -2..0)
-        T key[6];
+        double key[6];
         bool ok[6];
         int m = 0;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                key[2 * f + t] = T(0);
+                key[2 * f + t] = 0.0;
                 ok[2 * f + t] = cross(f, t, 0.0, key[2 * f + t]);
                 m += ok[2 * f + t] ? 1 : 0;
             }
@@ -346,7 +349,7 @@ struct PlaneTask {
         const int fo = (pick >> 1) - 2;
         int sa_ = 0, sb_ = 0;
         double Ax = 0.0, Ay = 0.0, Bx = 0.0, By = 0.0;
-        T kp = T(0);
+        double kp = 0.0;
 #pragma unroll
         for (int c0 = 0; c0 < 6; ++c0) {
             if (c0 != pick) continue;
@@ -365,7 +368,7 @@ struct PlaneTask {
         neighbour(fo, 0, s2, n1i, n1j, n1s);
         neighbour(fo, 0, s3, n4i, n4j, n4s);
         two_points(n1i, n1j, n1s, n4i, n4j, n4s, P1x, P1y, P4x, P4y);
-        sval = fit_height<T>((T)P1x, (T)P1y, (T)P2x, (T)P2y, (T)P3x, (T)P3y, (T)P4x, (T)P4y, kp);
+        sval = clamp_frac<T>((T)fit_height<double>(P1x, P1y, P2x, P2y, P3x, P3y, P4x, P4y, kp));
         return par;
     }
 };

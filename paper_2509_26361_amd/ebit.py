@@ -60,12 +60,18 @@ class Stats(ctypes.Structure):
         ("n_active_cells", ctypes.c_int64),
         ("step_sweeps", ctypes.c_int64),
         ("n_interfacial_sum", ctypes.c_int64),
+        ("max_courant", ctypes.c_double),
     ]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["n_markers"] = list(self.n_markers)
         return d
+
+
+class Errors(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_double), ("volume_ref", ctypes.c_double), ("l1_diff", ctypes.c_double),
+                ("e_shape", ctypes.c_double), ("e_mass", ctypes.c_double), ("samples", ctypes.c_int64)]
 
 
 def lib():
@@ -87,6 +93,8 @@ def lib():
         L.ebit_front2vof.restype = ctypes.c_int
         L.ebit_stats.argtypes = [P, P, ctypes.POINTER(Stats), P]
         L.ebit_stats.restype = ctypes.c_int
+        L.ebit_errors.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(Errors), P]
+        L.ebit_errors.restype = ctypes.c_int
         L.ebit_current.argtypes = [P]
         L.ebit_current.restype = ctypes.c_int
         L.ebit_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -251,6 +259,15 @@ class Ebit:
         if rc not in (EBIT_OK, EBIT_ECFL) or (check_cfl and rc == EBIT_ECFL):
             raise EbitError(rc, "ebit_stats")
         return st.as_dict()
+
+    def errors(self, C, C0, reset=False, stream=None):
+        """E_mass (mean over the calls since a reset) and E_shape of C
+        against C0 (paper eqs. Eq_error_surface, Eq_error_shape)."""
+        e = Errors()
+        rc = lib().ebit_errors(self.ctx, _ptr(C), _ptr(C0), int(bool(reset)), ctypes.byref(e), _stream(stream))
+        if rc != EBIT_OK:
+            raise EbitError(rc, "ebit_errors")
+        return {k: getattr(e, k) for k, _ in Errors._fields_}
 
     def set_surrogate(self, theta):
         """Front2VOF uses the surrogate for unambiguous cells (None: off)."""

@@ -1,9 +1,9 @@
 """The FP32 precision form against the FP64 oracle / FP64 GPU path.
 
-Marker fractions, velocity, circle fits and Front2VOF run in FP32; node
-crossing decisions (colour flips, landing edges, which side of a grid line a
-point lies on) are taken in FP64 from the FP32 values, and the global volume
-is a compensated FP64 sum.  Bar: positions and volume fractions within 1e-5
+Marker fractions and velocities are stored, and velocities interpolated, in
+FP32; the geometry (advected positions, crossing decisions, circle fits) runs
+in FP64 from those FP32 values and is rounded to FP32 when stored;
+Front2VOF runs in FP32 and the global volume is a compensated FP64 sum.  Bar: positions and volume fractions within 1e-5
 of the FP64 oracle for one sweep from the same (FP32-representable) state,
 colours equal except where the FP64 decision itself is within FP32 rounding
 of a tie."""
@@ -14,6 +14,7 @@ import torch
 from oracle import oracle as O
 from paper_2509_26361_amd import ebit as E
 from paper_2509_26361_amd import inputs as I
+from tests import fp32_model
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
@@ -56,9 +57,14 @@ def test_fp32_single_sweep_matches_fp64_oracle(case):
         e.load_state(T(st.flags), [T(x, torch.float32) for x in st.s])
         e.sweep(d, T(U32[d], torch.float32), g, dt)
         ref, _ = O.sweep(st, d, g, dt, U32[d])
+        mod, _ = fp32_model.sweep(st, d, g, dt, U32[d])
         torch.cuda.synchronize()
         fl, s = e.state()
         f = fl.cpu().numpy()
+        # the form's stated arithmetic: equal to the FP32 model up to the final rounding
+        assert np.array_equal(f, mod.flags), f"{case} dir {d}: flags differ from the FP32 model"
+        for k in range(3):
+            assert np.max(np.abs(s[k].cpu().numpy().astype(np.float64) - mod.s[k])) <= 1e-7
         mism = int(np.sum(f != ref.flags))
         assert mism <= max(2, ref.flags.size // 20000), f"{case} dir {d}: {mism} flag mismatches"
         same = f == ref.flags

@@ -27,37 +27,43 @@ def _errors(n, centre, vel, dt, steps, gfun):
         st, c = O.step(st, vel, gfun(s, dt), dt)
         tot += c
         C, _ = O.f2v(st)
-        em += abs(sum(O.volume(C)) - V0)
-    return em / steps / V0, np.abs(C - C0).sum() / C0.sum(), tot
+        V = sum(O.volume(C))
+        em += abs(V - V0)
+    return em / steps / V0, np.abs(C - C0).sum() / C0.sum(), tot, (V - V0) / V0
 
 
-def test_translation_errors_match_paper_table2():
-    """Translation with reversal at T/2, CFL 0.125, N = 32 (sec. 3.1): the
-    shape error matches the paper's Table 2 within 2 %, the mass error is of
-    the same size (within a factor 2)."""
+@pytest.mark.parametrize("n", [32, 64])
+def test_translation_errors_match_paper_table2(n):
+    """Translation with reversal at T/2, CFL 0.125 (sec. 3.1): the shape error
+    matches Table 2 within 1 % at N = 32 and 64 (measured: 0.1 %).  The mass
+    error is 1.42x (N = 32) and 1.69x (N = 64) the printed one; the band
+    asserted here records that gap, whose cause is not identified."""
     ref = json.load(open(os.path.join(GOLDEN, "translation_table2.json")))
-    n = 32
+    k = ref["N"].index(n)
     dt = 0.125 / n
     steps = int(round(1.0 / dt))
-    em, es, tot = _errors(n, (0.25, 0.25, 0.25), I.uniform_velocity(n), dt, steps,
+    em, es, tot, _ = _errors(n, (0.25, 0.25, 0.25), I.uniform_velocity(n), dt, steps,
                           lambda s, dt: 1.0 if s < steps // 2 else -1.0)
-    assert abs(es / ref["E_shape"][0] - 1.0) < 0.02, es
-    assert 0.5 < em / ref["E_mass"][0] < 2.0, em
+    assert abs(es / ref["E_shape"][k] - 1.0) < 0.01, es
+    assert 1.3 < em / ref["E_mass"][k] < 1.8, em
     assert tot[0] == 0 and tot[2] == 0
 
 
 def test_deformation_errors_same_order_as_paper_table3():
-    """3D deformation, T = 3, CFL 0.125 on v_max, N = 32 (sec. 3.2): errors
-    of the same order as Table 3 and a mass loss at this resolution, as the
-    paper reports for N = 32 and 64."""
+    """3D deformation, T = 3, CFL 0.125 on v_max, N = 32 (sec. 3.2): a mass
+    loss at T, as the paper reports for N = 32 and 64; errors below the
+    printed ones at this under-resolved size (measured: E_shape 0.67x,
+    E_mass 0.43x Table 3; at N = 128 the GPU path, identical to this oracle,
+    gives E_shape within 1 % of Table 3)."""
     ref = json.load(open(os.path.join(GOLDEN, "deformation_table3.json")))
     n = 32
     dt = 0.125 / n
     steps = int(round(3.0 / dt))
-    em, es, tot = _errors(n, (0.35, 0.35, 0.35), I.deformation_velocity(n), dt, steps,
-                          lambda s, dt: I.deformation_time_factor(s * dt, 3.0))
-    assert 0.3 < es / ref["E_shape"][0] < 3.0, es
-    assert 0.2 < em / ref["E_mass"][0] < 3.0, em
+    em, es, tot, dv = _errors(n, (0.35, 0.35, 0.35), I.deformation_velocity(n), dt, steps,
+                              lambda s, dt: I.deformation_time_factor(s * dt, 3.0))
+    assert dv < 0.0, dv
+    assert 0.6 < es / ref["E_shape"][0] < 0.75, es
+    assert 0.35 < em / ref["E_mass"][0] < 0.5, em
     assert tot[0] == 0 and tot[2] == 0
 
 
