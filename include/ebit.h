@@ -310,6 +310,44 @@ int ebit_set_surrogate(ebit_ctx *ctx, const float *theta);
  * Rows are ordered by chunk (deterministic).  Synchronises stream. */
 int ebit_surrogate_dataset(ebit_ctx *ctx, void *x_bf16, float *c, int64_t cap, int64_t *count, void *stream);
 
+/* ------------------------------------------------------------------------ *
+ * Coupling of C to a flow solver (sec. 2.5: the volume fraction from
+ * Front2VOF feeds a well-balanced continuum-surface-force term whose
+ * curvature comes from height functions).  Context-free: any n^3 periodic
+ * C field (doubles, or floats with EBIT_FP32; h = 1/n), device pointers,
+ * async on `stream`.  All arithmetic is FP64, in the order stated.
+ * ------------------------------------------------------------------------ */
+
+/* Curvature kappa (1/length) and a status per cell:
+ *   0  C is 0 or 1 (kappa 0)
+ *   1  height functions along the direction of the largest component of
+ *      Youngs' gradient (weights (1,2,1) x (1,2,1) over the 3x3 cells
+ *      across each axis of C(+1) - C(-1)); 2  along another one, tried in
+ *      decreasing order of that component (ties: lower axis)
+ *   3  no direction had heights: the mean of the neighbours (26, added in
+ *      z, y, x order) with status 1 or 2;  4  none had (kappa 0)
+ * Heights: for direction d the 9 columns at offsets -1..1 on the two other
+ * axes, 7 cells each (-3..3 along d); a column is valid when its end cells
+ * hold exactly 1 and 0, all 9 with the same orientation o (+1: phase 1 at
+ * -3).  z = sum - 7/2 (o = +1) or 7/2 - sum, summing from -3 up; with
+ * za, zb (central), zaa, zbb (second) and zab (cross, /4) differences of z,
+ * kappa = -o (zaa (1 + zb^2) + zbb (1 + za^2) - 2 zab za zb) / (t sqrt(t) h),
+ * t = 1 + za^2 + zb^2: positive where phase 1 is convex (2/R on a sphere).
+ *   kappa   n^3 (the precision's type), status n^3 bytes: outputs
+ *   work    device, >= ebit_curvature_work_bytes(n), 4-byte aligned: the list
+ *           of cells with 0 < C < 1 that the dense passes take
+ * EBIT_EINVAL for bad arguments, EBIT_ESCRATCH for a short work space. */
+size_t ebit_curvature_work_bytes(int32_t n);   /* device work space of ebit_curvature (0 for a bad n) */
+int ebit_curvature(int32_t n, int32_t precision, const void *C, void *kappa, uint8_t *status, void *work,
+                   size_t work_bytes, void *stream);
+
+/* CSF force density on the lower face of every cell along each axis:
+ * F_d(p) = sigma kappa_f (C(p) - C(p - e_d)) / h, with kappa_f the mean of
+ * the curvatures of the two cells that have status 1..3 (the one that has,
+ * 0 if neither).  F: 3 device pointers, n^3 each (outputs). */
+int ebit_csf(int32_t n, int32_t precision, const void *C, const void *kappa, const uint8_t *status, double sigma,
+             void *const *F, void *stream);
+
 /* Free the context (not the caller's buffers). */
 void ebit_destroy(ebit_ctx *ctx);
 

@@ -51,6 +51,8 @@ kappa_f = mean of the curvatures of those two cells that have status 1-3
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 STATUS_NONE, STATUS_HF, STATUS_HF_OTHER, STATUS_MEAN, STATUS_MISSING = 0, 1, 2, 3, 4
@@ -119,7 +121,8 @@ def _kappa_from_heights(z, o, h):
     zbb = z[1][2] - 2.0 * z[1][1] + z[1][0]
     zab = (z[2][2] - z[2][0] - z[0][2] + z[0][0]) / 4.0
     num = zaa * (1.0 + zb * zb) + zbb * (1.0 + za * za) - 2.0 * zab * za * zb
-    den = (1.0 + za * za + zb * zb) ** 1.5
+    t = 1.0 + za * za + zb * zb
+    den = t * math.sqrt(t)                     # t^(3/2)
     return -o * num / (den * h)
 
 

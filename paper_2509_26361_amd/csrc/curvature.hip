@@ -1,0 +1,295 @@
+// curvature.hip -- interface curvature by height functions and the
+// continuum-surface-force (CSF) term, from the volume fraction C that
+// Front2VOF produces (paper sec. 2.5: C is coupled to the flow solver through
+// a well-balanced CSF term with generalised height-function curvature).
+//
+// Curvature: a streaming pass over the whole periodic n^3 grid (x fastest,
+// one thread per cell, few registers) writes the zeros of the cells away from
+// the interface and compacts the cells with 0 < C < 1 into a list by wave
+// ballot; two dense passes over that list, one lane per cell, gather the
+// 3x3x7 stencils through the caches (the heights need many registers, which
+// would starve the streaming pass of occupancy).  The CSF pass streams the
+// grid again.  All arithmetic is FP64 (C in FP32 is widened on load) in the
+// order stated in include/ebit.h, so results are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/ebit.h"
+
+namespace {
+
+constexpr int kCurvBlock = 256;
+constexpr int kDenseBlocks = 1024;   // grid of the passes over the interfacial-cell list
+
+enum : uint8_t { KS_NONE = 0, KS_HF = 1, KS_HF_OTHER = 2, KS_MEAN = 3, KS_MISSING = 4 };
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+struct Grid {
+    const T *__restrict__ C;
+    int n;
+    __device__ __forceinline__ double at(int x, int y, int z) const
+    {
+        return (double)C[(long)wrapc(x, n) + (long)n * ((long)wrapc(y, n) + (long)n * (long)wrapc(z, n))];
+    }
+    __device__ __forceinline__ double at3(const int p[3]) const { return at(p[0], p[1], p[2]); }
+};
+
+// Youngs' gradient component along d: weights (1,2,1) x (1,2,1) over the
+// 3x3 cells across d (a on the lower other axis, outer; b inner)
+template <typename T>
+__device__ __forceinline__ double youngs(const Grid<T> &g, const int p[3], int d)
+{
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    double acc = 0.0;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b) {
+            const double w = (double)((2 - abs(a)) * (2 - abs(b)));
+            int up[3] = {p[0], p[1], p[2]}, dn[3] = {p[0], p[1], p[2]};
+            up[t1] += a; up[t2] += b; up[d] += 1;
+            dn[t1] += a; dn[t2] += b; dn[d] -= 1;
+            acc += w * (g.at3(up) - g.at3(dn));
+        }
+    return acc;
+}
+
+// Heights of the 9 columns of 7 cells along d; false when a column's ends
+// are not one full and one empty cell, or orientations differ.  The 63 loads
+// are issued before any test.
+template <typename T>
+__device__ __forceinline__ bool heights(const Grid<T> &g, const int p[3], int d, double z[3][3], int &orient)
+{
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    double col[3][3][7];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                int q[3] = {p[0], p[1], p[2]};
+                q[t1] += a - 1;
+                q[t2] += b - 1;
+                q[d] += k - 3;
+                col[a][b][k] = g.at3(q);
+            }
+    orient = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            int o;
+            if (col[a][b][0] == 1.0 && col[a][b][6] == 0.0) o = 1;
+            else if (col[a][b][0] == 0.0 && col[a][b][6] == 1.0) o = -1;
+            else return false;
+            if (orient && o != orient) return false;
+            orient = o;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) s += col[a][b][k];
+            z[a][b] = o == 1 ? s - 3.5 : 3.5 - s;
+        }
+    return true;
+}
+
+__device__ __forceinline__ double kappa_of(const double z[3][3], int o, double h)
+{
+    const double za = (z[2][1] - z[0][1]) / 2.0;
+    const double zb = (z[1][2] - z[1][0]) / 2.0;
+    const double zaa = z[2][1] - 2.0 * z[1][1] + z[0][1];
+    const double zbb = z[1][2] - 2.0 * z[1][1] + z[1][0];
+    const double zab = (z[2][2] - z[2][0] - z[0][2] + z[0][0]) / 4.0;
+    const double num = zaa * (1.0 + zb * zb) + zbb * (1.0 + za * za) - 2.0 * zab * za * zb;
+    const double t = 1.0 + za * za + zb * zb;
+    const double den = t * sqrt(t);
+    return ((double)(-o) * num) / (den * h);
+}
+
+// pass 1 (streaming, few registers): every cell's status 0 and curvature 0,
+// except the cells with 0 < C < 1, which are appended to a list (one atomic
+// add per wave, positions by ballot prefix) for the dense passes
+template <typename T>
+__global__ __launch_bounds__(kCurvBlock) void k_curv_scan(const T *__restrict__ C, long N, T *__restrict__ kap,
+                                                         uint8_t *__restrict__ status, uint32_t *__restrict__ list,
+                                                         unsigned *__restrict__ count)
+{
+    const long q = (long)blockIdx.x * kCurvBlock + threadIdx.x;
+    const bool in = q < N;
+    const double c = in ? (double)C[q] : 0.0;
+    const bool mixed = in && c > 0.0 && c < 1.0;
+    if (in) {
+        kap[q] = (T)0;
+        status[q] = mixed ? KS_MISSING : KS_NONE;
+    }
+    const unsigned long long bal = __ballot(mixed);
+    if (!bal) return;
+    const int lane = threadIdx.x & 63;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned)__popcll(bal));
+    base = __shfl(base, 0);
+    if (mixed) list[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)q;
+}
+
+// pass 2 (dense over the list, one lane per interfacial cell): height-function
+// curvature (status 1 or 2); status 4 stays where no direction has 9 valid
+// columns
+template <typename T>
+__global__ __launch_bounds__(kCurvBlock) void k_curv_hf(const T *__restrict__ C, int n, T *__restrict__ kap,
+                                                       uint8_t *__restrict__ status, const uint32_t *__restrict__ list,
+                                                       const unsigned *__restrict__ count)
+{
+    const unsigned m = *count;
+    const Grid<T> g{C, n};
+    const double h = 1.0 / (double)n;
+    for (unsigned i = blockIdx.x * kCurvBlock + threadIdx.x; i < m; i += gridDim.x * kCurvBlock) {
+        const long q = (long)list[i];
+        const int p[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / ((long)n * n))};
+        double gd[3];
+        for (int d = 0; d < 3; ++d) gd[d] = fabs(youngs(g, p, d));
+        // candidate order: decreasing |g_d|, ties by lower axis
+        int ord[3] = {0, 1, 2};
+        for (int a = 1; a < 3; ++a)
+            for (int b = a; b > 0 && gd[ord[b]] > gd[ord[b - 1]]; --b) {
+                const int t = ord[b]; ord[b] = ord[b - 1]; ord[b - 1] = t;
+            }
+        for (int r = 0; r < 3; ++r) {
+            double z[3][3];
+            int o;
+            if (!heights(g, p, ord[r], z, o)) continue;
+            kap[q] = (T)kappa_of(z, o, h);
+            status[q] = r == 0 ? KS_HF : KS_HF_OTHER;
+            break;
+        }
+    }
+}
+
+// pass 3 (over the list): a cell without heights takes the mean curvature of
+// its neighbours that have one (status 1 or 2, never changed by this pass),
+// in [k][j][i] order
+template <typename T>
+__global__ __launch_bounds__(kCurvBlock) void k_curv_fill(int n, T *__restrict__ kap, uint8_t *__restrict__ status,
+                                                         const uint32_t *__restrict__ list,
+                                                         const unsigned *__restrict__ count)
+{
+    const unsigned m = *count;
+    for (unsigned i = blockIdx.x * kCurvBlock + threadIdx.x; i < m; i += gridDim.x * kCurvBlock) {
+        const long q = (long)list[i];
+        if (status[q] != KS_MISSING) continue;
+        const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / ((long)n * n));
+        double s = 0.0;
+        int cnt = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    const long r = (long)wrapc(x + dx, n) +
+                                   (long)n * ((long)wrapc(y + dy, n) + (long)n * (long)wrapc(z + dz, n));
+                    const uint8_t t = status[r];
+                    if (t == KS_HF || t == KS_HF_OTHER) {
+                        s += (double)kap[r];
+                        ++cnt;
+                    }
+                }
+        if (cnt) {
+            kap[q] = (T)(s / (double)cnt);
+            status[q] = KS_MEAN;
+        }
+    }
+}
+
+__global__ void k_curv_zero(unsigned *count) { *count = 0u; }
+
+// CSF force on the lower face of every cell along each axis
+template <typename T>
+__global__ __launch_bounds__(kCurvBlock) void k_csf(const T *__restrict__ C, const T *__restrict__ kap,
+                                                   const uint8_t *__restrict__ status, int n, double sigma,
+                                                   T *__restrict__ F0, T *__restrict__ F1, T *__restrict__ F2)
+{
+    const long N = (long)n * n * n;
+    const long q = (long)blockIdx.x * kCurvBlock + threadIdx.x;
+    if (q >= N) return;
+    const int p[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / ((long)n * n))};
+    const long str[3] = {1, (long)n, (long)n * n};
+    const double c = (double)C[q];
+    const double k = (double)kap[q];
+    const uint8_t sv = status[q];
+    const bool v = sv >= KS_HF && sv <= KS_MEAN;
+    const double h = 1.0 / (double)n;
+    T *const F[3] = {F0, F1, F2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const long r = p[d] == 0 ? q + (long)(n - 1) * str[d] : q - str[d];
+        const double cm = (double)C[r];
+        double f = 0.0;
+        if (cm != c) {
+            const uint8_t sm = status[r];
+            const bool vm = sm >= KS_HF && sm <= KS_MEAN;
+            const double km = (double)kap[r];
+            const double kf = (v && vm) ? (k + km) / 2.0 : (v ? k : (vm ? km : 0.0));
+            f = ((sigma * kf) * (c - cm)) / h;
+        }
+        F[d][q] = (T)f;
+    }
+}
+
+inline bool grid_ok(int n, int precision) { return n >= 8 && n <= 1024 && (precision == EBIT_FP64 || precision == EBIT_FP32); }
+
+}  // namespace
+
+extern "C" {
+
+size_t ebit_curvature_work_bytes(int32_t n)
+{
+    if (n < 8 || n > 1024) return 0;
+    return 256 + (size_t)n * n * n * sizeof(uint32_t);
+}
+
+int ebit_curvature(int32_t n, int32_t precision, const void *C, void *kappa, uint8_t *status, void *work,
+                   size_t work_bytes, void *stream)
+{
+    if (!grid_ok(n, precision) || !C || !kappa || !status || !work || ((uintptr_t)work & 3)) return EBIT_EINVAL;
+    if (work_bytes < ebit_curvature_work_bytes(n)) return EBIT_ESCRATCH;
+    const long N = (long)n * n * n;
+    const dim3 grid((unsigned)((N + kCurvBlock - 1) / kCurvBlock));
+    const dim3 dense(kDenseBlocks);
+    unsigned *count = (unsigned *)work;
+    uint32_t *list = (uint32_t *)((char *)work + 256);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, count);
+    if (precision == EBIT_FP64) {
+        hipLaunchKernelGGL(k_curv_scan<double>, grid, dim3(kCurvBlock), 0, st, (const double *)C, N, (double *)kappa,
+                           status, list, count);
+        hipLaunchKernelGGL(k_curv_hf<double>, dense, dim3(kCurvBlock), 0, st, (const double *)C, n, (double *)kappa,
+                           status, (const uint32_t *)list, (const unsigned *)count);
+        hipLaunchKernelGGL(k_curv_fill<double>, dense, dim3(kCurvBlock), 0, st, n, (double *)kappa, status,
+                           (const uint32_t *)list, (const unsigned *)count);
+    } else {
+        hipLaunchKernelGGL(k_curv_scan<float>, grid, dim3(kCurvBlock), 0, st, (const float *)C, N, (float *)kappa,
+                           status, list, count);
+        hipLaunchKernelGGL(k_curv_hf<float>, dense, dim3(kCurvBlock), 0, st, (const float *)C, n, (float *)kappa,
+                           status, (const uint32_t *)list, (const unsigned *)count);
+        hipLaunchKernelGGL(k_curv_fill<float>, dense, dim3(kCurvBlock), 0, st, n, (float *)kappa, status,
+                           (const uint32_t *)list, (const unsigned *)count);
+    }
+    return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
+}
+
+int ebit_csf(int32_t n, int32_t precision, const void *C, const void *kappa, const uint8_t *status, double sigma,
+             void *const *F, void *stream)
+{
+    if (!grid_ok(n, precision) || !C || !kappa || !status || !F || !F[0] || !F[1] || !F[2]) return EBIT_EINVAL;
+    const long N = (long)n * n * n;
+    const dim3 grid((unsigned)((N + kCurvBlock - 1) / kCurvBlock));
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == EBIT_FP64)
+        hipLaunchKernelGGL(k_csf<double>, grid, dim3(kCurvBlock), 0, st, (const double *)C, (const double *)kappa,
+                           status, n, sigma, (double *)F[0], (double *)F[1], (double *)F[2]);
+    else
+        hipLaunchKernelGGL(k_csf<float>, grid, dim3(kCurvBlock), 0, st, (const float *)C, (const float *)kappa,
+                           status, n, sigma, (float *)F[0], (float *)F[1], (float *)F[2]);
+    return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
+}
+
+}  // extern "C"

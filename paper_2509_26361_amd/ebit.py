@@ -95,6 +95,12 @@ def lib():
         L.ebit_stats.restype = ctypes.c_int
         L.ebit_errors.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(Errors), P]
         L.ebit_errors.restype = ctypes.c_int
+        L.ebit_curvature_work_bytes.argtypes = [ctypes.c_int32]
+        L.ebit_curvature_work_bytes.restype = ctypes.c_size_t
+        L.ebit_curvature.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, P]
+        L.ebit_curvature.restype = ctypes.c_int
+        L.ebit_csf.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_double, P, P]
+        L.ebit_csf.restype = ctypes.c_int
         L.ebit_current.argtypes = [P]
         L.ebit_current.restype = ctypes.c_int
         L.ebit_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -301,6 +307,47 @@ class Ebit:
             self._destroy()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# coupling of C to a flow solver: height-function curvature, CSF force
+# ----------------------------------------------------------------------------
+
+def _precision_of(t):
+    if t.dtype == torch.float64:
+        return EBIT_FP64
+    if t.dtype == torch.float32:
+        return EBIT_FP32
+    raise ValueError("C must be float64 or float32")
+
+
+def curvature(C, kappa=None, status=None, work=None, stream=None):
+    """Height-function curvature of a cubic (n, n, n) C field: (kappa,
+    status) device tensors (ebit_curvature)."""
+    n = C.shape[0]
+    if kappa is None:
+        kappa = torch.empty_like(C)
+    if status is None:
+        status = torch.empty(C.shape, dtype=torch.uint8, device=C.device)
+    if work is None:
+        work = torch.empty(lib().ebit_curvature_work_bytes(n), dtype=torch.uint8, device=C.device)
+    rc = lib().ebit_curvature(n, _precision_of(C), _ptr(C), _ptr(kappa), _ptr(status), _ptr(work), work.numel(),
+                              _stream(stream))
+    if rc != EBIT_OK:
+        raise EbitError(rc, "ebit_curvature")
+    return kappa, status
+
+
+def csf(C, kappa, status, sigma, F=None, stream=None):
+    """CSF face forces [F_x, F_y, F_z] (ebit_csf)."""
+    if F is None:
+        F = [torch.empty_like(C) for _ in range(3)]
+    arr = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F])
+    rc = lib().ebit_csf(C.shape[0], _precision_of(C), _ptr(C), _ptr(kappa), _ptr(status), float(sigma),
+                        ctypes.cast(arr, ctypes.c_void_p), _stream(stream))
+    if rc != EBIT_OK:
+        raise EbitError(rc, "ebit_csf")
+    return F
 
 
 # ----------------------------------------------------------------------------
