@@ -129,3 +129,38 @@ def test_mixed_512_fp32_forms_ordered_equal_claim_order(workload, surrogate):
         assert torch.equal(sa[k], sb[k]), k
     assert torch.equal(Ca, Cb)
     assert a.stats(Ca)["n_interfacial_sum"] == b.stats(Cb)["n_interfacial_sum"]
+
+
+def test_mixed_512_step_against_oracle(workload):
+    """Oracle parity at full size in the default launch configuration
+    (brick-ordered lists, runs, sparse task loads, directional band, fused
+    Front2VOF): after STEPS GPU steps the state goes to the oracle, both take
+    one more step (three sweeps, then Front2VOF), and every node and cell is
+    compared -- flags bit-exact, fractions and C within 1e-12."""
+    from oracle import oracle as O
+    phi, pf, U = workload
+    e = E.Ebit(N, "fp64", dev())
+    e.init(phi, pf)
+    C = torch.zeros((N, N, N), dtype=torch.float64, device=dev())
+    e.front2vof(C)
+    e.advance(U, [1.0] * STEPS, 0.5 / N, C)
+    torch.cuda.synchronize()
+    fl, s = e.state()
+    st = O.State(N, fl.cpu().numpy().copy(), [x.cpu().numpy() for x in s])
+    e.advance(U, [1.0], 0.5 / N, C)
+    torch.cuda.synchronize()
+    Uh = [u.cpu().numpy() for u in U]
+    st, cnt = O.step(st, Uh, 1.0, 0.5 / N)
+    del Uh
+    assert cnt[0] == 0 and cnt[2] == 0
+    fl, s = e.state()
+    f = fl.cpu().numpy()
+    bad = np.argwhere(f != st.flags)
+    assert len(bad) == 0, f"{len(bad)} flag mismatches, first at {bad[:3].tolist()}"
+    del f
+    for k in range(3):
+        d = float(np.max(np.abs(s[k].cpu().numpy() - st.s[k])))
+        assert d <= 1e-12, f"s[{k}] differs by {d}"
+    Co, _ = O.f2v(st)
+    d = float(np.max(np.abs(C.cpu().numpy() - Co)))
+    assert d <= 1e-12, f"C differs by {d}"

@@ -41,8 +41,35 @@ def test_forward_matches_oracle(m):
     assert np.mean(np.abs(y - yo)) < 2e-4
 
 
+def _abs_terms(th, X, c):
+    """For every gradient entry, the sum of the absolute values of the terms
+    the kernel adds (the bf16-mode oracle's products with every factor made
+    non-negative): the scale of the entry's rounding error."""
+    p = M.unpack(th)
+    y, t = M.forward(th, X, bf16_mode=True, keep=True)
+    m = X.shape[0]
+    dz3 = np.abs((2.0 / m) * (y - c) * y * (1.0 - y))
+    g = {}
+    g["w3"] = np.abs(t["h2"]).T @ dz3
+    g["b3"] = np.array([dz3.sum()])
+    dz2 = np.outer(dz3, np.abs(p["w3"])) * (t["z2"] > 0)
+    g["b2"] = dz2.sum(axis=0)
+    dz2r = M.bf16(dz2)
+    g["W2"] = np.abs(t["h1r"]).T @ dz2r
+    dh1 = dz2r @ np.abs(t["W2"]).T
+    dz1 = dh1 * (t["z1"] > 0)
+    g["b1"] = dz1.sum(axis=0)
+    g["W1"] = np.abs(t["X"]).T @ M.bf16(dz1)
+    return M.pack(g)
+
+
 @pytest.mark.parametrize("m", [64, 333, 5000])
 def test_gradient_matches_oracle(m):
+    """Element by element against the oracle evaluated with the kernels'
+    bfloat16 rounding points: each entry within 2^-6 of the sum of the
+    absolute values of its terms (a bfloat16 rounding that goes the other
+    way in one term moves the entry by at most 2^-8 of that term; FP32
+    accumulation adds m 2^-24), and 99.9 % of the entries within 2^-10."""
     rng = np.random.default_rng(m + 7)
     th, tg = theta32(2)
     th = th.astype(np.float32).astype(np.float64)
@@ -52,15 +79,14 @@ def test_gradient_matches_oracle(m):
     g, loss = tr.gradient(to_bf16_rows(X), torch.from_numpy(c.astype(np.float32)).to(dev()))
     lo, go = M.loss_and_grad(th, X, c, bf16_mode=True)
     g = g.cpu().numpy().astype(np.float64)
-    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
-    assert rel < 2e-2, rel
-    # per parameter block
+    scale = _abs_terms(th, X, c) + 1e-30
+    r = np.abs(g - go) / scale
     o = 0
     for name, shp in M.SIZES:
         k = int(np.prod(shp))
-        rb = np.linalg.norm(g[o:o + k] - go[o:o + k]) / (np.linalg.norm(go[o:o + k]) + 1e-30)
-        assert rb < 3e-2, (name, rb)
+        assert r[o:o + k].max() <= 2.0 ** -6, (name, float(r[o:o + k].max()))
         o += k
+    assert np.quantile(r, 0.999) <= 2.0 ** -10, float(np.quantile(r, 0.999))
     assert abs(float(loss.item()) - lo) < 1e-4 * max(1.0, lo)
 
 
