@@ -348,6 +348,22 @@ int ebit_curvature(int32_t n, int32_t precision, const void *C, void *kappa, uin
 int ebit_csf(int32_t n, int32_t precision, const void *C, const void *kappa, const uint8_t *status, double sigma,
              void *const *F, void *stream);
 
+/* The AMR-compatible refinement band (sec. 2.3: every cell of the 3x3x3
+ * block around an interfacial cell is refined to the finest level; with a
+ * Courant number of at most one the next step's interface stays inside it).
+ * From a state's flags (n^3, the layout above; e.g. buffer ebit_current()):
+ *   mask       n^3 bytes out: 1 where a cell lies in the 3x3x3 block of a cell
+ *              with a marker on any of its 12 edges, else 0
+ *   bricks     (n/4)^3 bytes out, brick (bx, by, bz) at bx + (n/4)(by + (n/4) bz):
+ *              1 where one of its 4^3 cells is in the mask (block-structured
+ *              refinement)
+ *   mask_prev  NULL, or an earlier mask (n^3 bytes) to check against
+ *   counts     4 device int64 out: interfacial cells, cells in the mask, bricks,
+ *              interfacial cells outside mask_prev (0 without it)
+ * n a multiple of 4.  Async on `stream`. */
+int ebit_refine_band(int32_t n, const uint8_t *flags, const uint8_t *mask_prev, uint8_t *mask, uint8_t *bricks,
+                     int64_t *counts, void *stream);
+
 /* Free the context (not the caller's buffers). */
 void ebit_destroy(ebit_ctx *ctx);
 

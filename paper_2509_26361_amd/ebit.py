@@ -101,6 +101,8 @@ def lib():
         L.ebit_curvature.restype = ctypes.c_int
         L.ebit_csf.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_double, P, P]
         L.ebit_csf.restype = ctypes.c_int
+        L.ebit_refine_band.argtypes = [ctypes.c_int32, P, P, P, P, P, P]
+        L.ebit_refine_band.restype = ctypes.c_int
         L.ebit_current.argtypes = [P]
         L.ebit_current.restype = ctypes.c_int
         L.ebit_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -348,6 +350,20 @@ def csf(C, kappa, status, sigma, F=None, stream=None):
     if rc != EBIT_OK:
         raise EbitError(rc, "ebit_csf")
     return F
+
+
+def refine_band(flags, mask_prev=None, stream=None):
+    """(mask, bricks, counts[interfacial, masked, bricks, escaped]) of a
+    state's flags (ebit_refine_band); counts is a device int64 tensor."""
+    n = flags.shape[0]
+    mask = torch.empty_like(flags)
+    bricks = torch.empty((n // 4,) * 3, dtype=torch.uint8, device=flags.device)
+    counts = torch.empty(4, dtype=torch.int64, device=flags.device)
+    rc = lib().ebit_refine_band(n, _ptr(flags), _ptr(mask_prev), _ptr(mask), _ptr(bricks), _ptr(counts),
+                                _stream(stream))
+    if rc != EBIT_OK:
+        raise EbitError(rc, "ebit_refine_band")
+    return mask, bricks, counts
 
 
 # ----------------------------------------------------------------------------

@@ -164,3 +164,11 @@ def test_mixed_512_step_against_oracle(workload):
     Co, _ = O.f2v(st)
     d = float(np.max(np.abs(C.cpu().numpy() - Co)))
     assert d <= 1e-12, f"C differs by {d}"
+    del Co
+    # the refinement band of this state (sec. 2.3) against its oracle
+    from oracle import refine as Rf
+    mask, bricks, counts = E.refine_band(fl)
+    wm = Rf.refine_mask(st.flags)
+    assert np.array_equal(mask.cpu().numpy(), wm.astype(np.uint8))
+    assert np.array_equal(bricks.cpu().numpy(), Rf.refine_bricks(wm).astype(np.uint8))
+    assert counts.cpu().tolist()[:2] == [int(Rf.interfacial(st.flags).sum()), int(wm.sum())]

@@ -1,0 +1,74 @@
+"""The refinement band (ebit_refine_band) against its oracle
+(oracle/refine.py): mask, bricks and counts bit-exact on random and sphere
+states, a ragged grid (the last tile along x half empty), the escape count
+after steps, and the 256^3 benchmark state and the 512^3 mixed state."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import refine as Rf
+from paper_2509_26361_amd import ebit as E
+from paper_2509_26361_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def check(flags_np, prev_np=None):
+    f = torch.from_numpy(np.ascontiguousarray(flags_np)).to(dev())
+    prev = torch.from_numpy(prev_np.astype(np.uint8)).to(dev()) if prev_np is not None else None
+    mask, bricks, counts = E.refine_band(f, prev)
+    torch.cuda.synchronize()
+    wm = Rf.refine_mask(flags_np)
+    wb = Rf.refine_bricks(wm)
+    assert np.array_equal(mask.cpu().numpy(), wm.astype(np.uint8))
+    assert np.array_equal(bricks.cpu().numpy(), wb.astype(np.uint8))
+    want = [int(Rf.interfacial(flags_np).sum()), int(wm.sum()), int(wb.sum()),
+            Rf.escaped(flags_np, prev_np) if prev_np is not None else 0]
+    assert counts.cpu().tolist() == want, (counts.cpu().tolist(), want)
+    return wm
+
+
+@pytest.mark.parametrize("n", [32, 36, 64])
+def test_random_states(n):
+    check(O.init(I.random_shape(n, n), exact=True).flags)
+
+
+def test_escape_count_over_steps():
+    n = 40
+    st = O.init(I.random_shape(n, 2), exact=True)
+    U = I.fourier_velocity(n, seed=3, modes=4)
+    prev = check(st.flags)
+    for g in (1.0, -1.0, 0.7):
+        st, _ = O.step(st, U, g, 1.0 / n)
+        prev = check(st.flags, prev)
+    # a deliberately stale mask: two unit-Courant translations
+    st = O.init(I.sphere_shape(n, (0.5, 0.5, 0.5), 0.2), exact=True)
+    m0 = Rf.refine_mask(st.flags)
+    for _ in range(2):
+        st, _ = O.step(st, I.uniform_velocity(n), 1.0, 1.0 / n)
+    check(st.flags, m0)
+    assert Rf.escaped(st.flags, m0) > 0
+
+
+def test_full_size_states():
+    n = 256
+    sh = I.sphere_shape(n)
+    e = E.Ebit(n, "fp64", dev())
+    e.init(torch.from_numpy(sh.phi_nodes).to(dev()), [torch.from_numpy(f).to(dev()) for f in sh.phi_faces])
+    U = [torch.from_numpy(u).to(dev()) for u in I.deformation_velocity(n)]
+    C = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    e.front2vof(C)
+    e.advance(U, [I.deformation_time_factor(k * 0.5 / n, 3.0) for k in range(300)], 0.5 / n, C)
+    torch.cuda.synchronize()
+    f0 = e.state()[0].cpu().numpy().copy()
+    m0 = check(f0)
+    e.advance(U, [I.deformation_time_factor(300 * 0.5 / n, 3.0)], 0.5 / n, C)
+    torch.cuda.synchronize()
+    check(e.state()[0].cpu().numpy(), m0)
