@@ -140,7 +140,7 @@ def stored_traffic(kernel, window):
     return None
 
 
-def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8):
+def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8, keep=False):
     """W untimed steps, then K timed steps of the deformation workload
     (Front2VOF through the learned surrogate when `theta` is given)."""
     T_end = 3.0
@@ -173,7 +173,56 @@ def run_case(E, I, torch, n, precision, W, K, events, theta=None, every=8):
     st1 = e.stats(C)
     n_start = st0["n_interfacial"] + (st1["n_interfacial_sum"] - st0["n_interfacial_sum"]) - st1["n_interfacial"]
     kt = launch_times(tm)
-    return {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "kt": kt}
+    out = {"wall": wall, "n_start": n_start, "st0": st0, "st1": st1, "kt": kt}
+    if keep:
+        out["ebit"], out["C"] = e, C
+    return out
+
+
+# algorithmic bytes per cell of the coupling kernels (full grid, FP64):
+#   curvature: read C, write kappa and the status byte; CSF: read C, kappa,
+#   status, write the three face forces; refinement band: read the flags,
+#   write the mask (and a byte per 4^3 brick)
+COUPLING_BYTES = {"curvature": 8 + 8 + 1, "csf": 8 + 8 + 1 + 3 * 8, "refine_band": 1 + 1 + 1.0 / 64}
+
+
+def coupling_kernels(E, torch, e, C, reps=20):
+    """Mean durations of the coupling entry points on the state at the end of
+    the timed steps (HIP events on the stream they run on), and their rate
+    on the algorithmic bytes of the whole grid."""
+    n = C.shape[0]
+    stream = torch.cuda.current_stream()
+    kap = torch.empty_like(C)
+    status = torch.empty(C.shape, dtype=torch.uint8, device=C.device)
+    work = torch.empty(E.lib().ebit_curvature_work_bytes(n), dtype=torch.uint8, device=C.device)
+    F = [torch.empty_like(C) for _ in range(3)]
+    flags = e.state()[0]
+    rb_out = (torch.empty_like(flags), torch.empty((n // 4,) * 3, dtype=torch.uint8, device=C.device),
+              torch.empty(4, dtype=torch.int64, device=C.device),
+              torch.empty(E.lib().ebit_refine_work_bytes(n), dtype=torch.uint8, device=C.device))
+    calls = {
+        "curvature": lambda: E.curvature(C, kap, status, work),
+        "csf": lambda: E.csf(C, kap, status, 0.0728, F),
+        "refine_band": lambda: E.refine_band(flags, out=rb_out),
+    }
+    out = {}
+    for name, f in calls.items():
+        for _ in range(3):
+            f()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            f()
+        b.record(stream)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / reps
+        gbs = COUPLING_BYTES[name] * n ** 3 / (us * 1e-6) / 1e9
+        out[name] = {"us": us, "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                     "bytes_per_cell": COUPLING_BYTES[name]}
+    st = status.cpu()
+    out["curvature"]["cells"] = {"interfacial": int((st > 0).sum()), "height_function": int(((st == 1) | (st == 2)).sum()),
+                                 "neighbour_mean": int((st == 3).sum()), "none": int((st == 4).sum())}
+    return out
 
 
 def accuracy_run(E, I, torch, n, precision, theta=None):
@@ -245,9 +294,10 @@ def main():
     # the same window again from the same initial state, launches bracketed with HIP events
     # (every `every`-th of each kind; the brackets hold back the next dispatch, so this pass is
     # slower as a whole and serves only the per-launch durations)
-    rb = run_case(E, I, torch, n, a.precision, W, K, events=True, every=every)
+    rb = run_case(E, I, torch, n, a.precision, W, K, events=True, every=every, keep=True)
     assert rb["n_start"] == n_start, "the bracketed pass took a different path"
     kt = rb["kt"]
+    coupling = coupling_kernels(E, torch, rb.pop("ebit"), rb.pop("C"))
     dom, kinds = roofline(kt, units_per_launch, a.precision, window)
     out = {
         "metric": "interfacial cell-updates/s (advect+Front2VOF), 256^3; vol err vs FP64",
@@ -276,6 +326,7 @@ def main():
         "volume": {"start": st0["volume"] + st0["volume_comp"], "end": st1["volume"] + st1["volume_comp"]},
         "counters": {k: st1[k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged", "max_courant")},
         "band_bricks_per_sweep": (st1["n_active_cells"] - st0["n_active_cells"]) / 64.0 / (3 * K),
+        "coupling_kernels": coupling,
     }
     print(f"[bench] {a.precision}: {out['ms_per_step']:.3f} ms/step, {value:.3e} cells/s", file=sys.stderr, flush=True)
     del r

@@ -360,9 +360,13 @@ int ebit_csf(int32_t n, int32_t precision, const void *C, const void *kappa, con
  *   mask_prev  NULL, or an earlier mask (n^3 bytes) to check against
  *   counts     4 device int64 out: interfacial cells, cells in the mask, bricks,
  *              interfacial cells outside mask_prev (0 without it)
- * n a multiple of 4.  Async on `stream`. */
+ *   work       device, >= ebit_refine_work_bytes(n) (16 KB), 8-byte aligned: partial counts
+ * flags, mask and mask_prev must be 4-byte aligned (whole words are read and written).
+ * n a multiple of 4.  Async on `stream`.  EBIT_EINVAL / EBIT_ESCRATCH on bad
+ * arguments. */
+size_t ebit_refine_work_bytes(int32_t n);
 int ebit_refine_band(int32_t n, const uint8_t *flags, const uint8_t *mask_prev, uint8_t *mask, uint8_t *bricks,
-                     int64_t *counts, void *stream);
+                     int64_t *counts, void *work, size_t work_bytes, void *stream);
 
 /* Free the context (not the caller's buffers). */
 void ebit_destroy(ebit_ctx *ctx);

@@ -20,7 +20,19 @@
 namespace {
 
 constexpr int kCurvBlock = 256;
-constexpr int kDenseBlocks = 1024;   // grid of the passes over the interfacial-cell list
+// The list is kLists sub-lists, each with its own append counter on a cache
+// line of its own: workgroup b of the streaming pass appends to sub-list
+// b % kLists, one atomic add per workgroup, so the appends of the whole grid
+// spread over kLists addresses instead of queueing on one.
+constexpr int kLists = 256;
+constexpr int kDenseBlocks = 1024;   // grid of the dense passes (grid-stride over the listed cells)
+constexpr int kCtrStride = 32;       // 128 bytes between counters
+
+inline long list_cap(long N)
+{
+    const long blocks = (N + kCurvBlock - 1) / kCurvBlock;
+    return ((blocks + kLists - 1) / kLists) * kCurvBlock;   // the cells of every workgroup that appends to it
+}
 
 enum : uint8_t { KS_NONE = 0, KS_HF = 1, KS_HF_OTHER = 2, KS_MEAN = 3, KS_MISSING = 4 };
 
@@ -113,8 +125,10 @@ __device__ __forceinline__ double kappa_of(const double z[3][3], int o, double h
 template <typename T>
 __global__ __launch_bounds__(kCurvBlock) void k_curv_scan(const T *__restrict__ C, long N, T *__restrict__ kap,
                                                          uint8_t *__restrict__ status, uint32_t *__restrict__ list,
-                                                         unsigned *__restrict__ count)
+                                                         unsigned *__restrict__ count, long cap)
 {
+    __shared__ unsigned wcnt[kCurvBlock / 64];
+    __shared__ unsigned base;
     const long q = (long)blockIdx.x * kCurvBlock + threadIdx.x;
     const bool in = q < N;
     const double c = in ? (double)C[q] : 0.0;
@@ -123,14 +137,58 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_scan(const T *__restrict__ 
         kap[q] = (T)0;
         status[q] = mixed ? KS_MISSING : KS_NONE;
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long bal = __ballot(mixed);
-    if (!bal) return;
-    const int lane = threadIdx.x & 63;
-    unsigned base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned)__popcll(bal));
-    base = __shfl(base, 0);
-    if (mixed) list[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)q;
+    if (lane == 0) wcnt[wave] = (unsigned)__popcll(bal);
+    __syncthreads();
+    unsigned before = 0, tot = 0;
+    for (int w = 0; w < kCurvBlock / 64; ++w) {
+        before += w < wave ? wcnt[w] : 0u;
+        tot += wcnt[w];
+    }
+    if (tot == 0) return;                      // uniform over the workgroup
+    const int sub = (int)(blockIdx.x % kLists);
+    if (threadIdx.x == 0) base = atomicAdd(&count[sub * kCtrStride], tot);
+    __syncthreads();
+    if (mixed) list[(long)sub * cap + base + before + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)q;
 }
+
+// The sub-lists taken as one range: pre[k] = cells in sub-lists before k
+// (one workgroup of kLists threads scans the kLists counters in LDS), and
+// cell i of the range lies in the last sub-list k with pre[k] <= i.
+struct ListRange {
+    uint32_t *pre;   // kLists + 1 entries in LDS
+    __device__ __forceinline__ void build(const unsigned *__restrict__ count, uint32_t *wtot)
+    {
+        const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+        const uint32_t c = count[t * kCtrStride];
+        uint32_t v = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t u = __shfl_up(v, off);
+            if (lane >= off) v += u;
+        }
+        if (lane == 63) wtot[wave] = v;
+        __syncthreads();
+        uint32_t run = v - c;
+        for (int w = 0; w < wave; ++w) run += wtot[w];
+        pre[t] = run;
+        if (t == kLists - 1) pre[kLists] = run + c;
+        __syncthreads();
+    }
+    __device__ __forceinline__ uint32_t total() const { return pre[kLists]; }
+    __device__ __forceinline__ long cell(const uint32_t *__restrict__ list, long cap, uint32_t i) const
+    {
+        int lo = 0, hi = kLists;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        return (long)list[(long)lo * cap + (i - pre[lo])];
+    }
+};
+static_assert(kCurvBlock == kLists, "one thread per sub-list counter in ListRange::build");
 
 // pass 2 (dense over the list, one lane per interfacial cell): height-function
 // curvature (status 1 or 2); status 4 stays where no direction has 9 valid
@@ -138,13 +196,15 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_scan(const T *__restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kCurvBlock) void k_curv_hf(const T *__restrict__ C, int n, T *__restrict__ kap,
                                                        uint8_t *__restrict__ status, const uint32_t *__restrict__ list,
-                                                       const unsigned *__restrict__ count)
+                                                       const unsigned *__restrict__ count, long cap)
 {
-    const unsigned m = *count;
+    __shared__ uint32_t pre[kLists + 1], wtot[kCurvBlock / 64];
+    ListRange lr{pre};
+    lr.build(count, wtot);
     const Grid<T> g{C, n};
     const double h = 1.0 / (double)n;
-    for (unsigned i = blockIdx.x * kCurvBlock + threadIdx.x; i < m; i += gridDim.x * kCurvBlock) {
-        const long q = (long)list[i];
+    for (uint32_t i = blockIdx.x * kCurvBlock + threadIdx.x; i < lr.total(); i += gridDim.x * kCurvBlock) {
+        const long q = lr.cell(list, cap, i);
         const int p[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / ((long)n * n))};
         double gd[3];
         for (int d = 0; d < 3; ++d) gd[d] = fabs(youngs(g, p, d));
@@ -171,11 +231,13 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_hf(const T *__restrict__ C,
 template <typename T>
 __global__ __launch_bounds__(kCurvBlock) void k_curv_fill(int n, T *__restrict__ kap, uint8_t *__restrict__ status,
                                                          const uint32_t *__restrict__ list,
-                                                         const unsigned *__restrict__ count)
+                                                         const unsigned *__restrict__ count, long cap)
 {
-    const unsigned m = *count;
-    for (unsigned i = blockIdx.x * kCurvBlock + threadIdx.x; i < m; i += gridDim.x * kCurvBlock) {
-        const long q = (long)list[i];
+    __shared__ uint32_t pre[kLists + 1], wtot[kCurvBlock / 64];
+    ListRange lr{pre};
+    lr.build(count, wtot);
+    for (uint32_t i = blockIdx.x * kCurvBlock + threadIdx.x; i < lr.total(); i += gridDim.x * kCurvBlock) {
+        const long q = lr.cell(list, cap, i);
         if (status[q] != KS_MISSING) continue;
         const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / ((long)n * n));
         double s = 0.0;
@@ -199,7 +261,10 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_fill(int n, T *__restrict__
     }
 }
 
-__global__ void k_curv_zero(unsigned *count) { *count = 0u; }
+__global__ void k_curv_zero(unsigned *count)
+{
+    for (int k = threadIdx.x; k < kLists; k += blockDim.x) count[k * kCtrStride] = 0u;
+}
 
 // CSF force on the lower face of every cell along each axis
 template <typename T>
@@ -243,7 +308,8 @@ extern "C" {
 size_t ebit_curvature_work_bytes(int32_t n)
 {
     if (n < 8 || n > 1024) return 0;
-    return 256 + (size_t)n * n * n * sizeof(uint32_t);
+    const long N = (long)n * n * n;
+    return (size_t)kLists * kCtrStride * sizeof(unsigned) + (size_t)kLists * list_cap(N) * sizeof(uint32_t);
 }
 
 int ebit_curvature(int32_t n, int32_t precision, const void *C, void *kappa, uint8_t *status, void *work,
@@ -254,24 +320,25 @@ int ebit_curvature(int32_t n, int32_t precision, const void *C, void *kappa, uin
     const long N = (long)n * n * n;
     const dim3 grid((unsigned)((N + kCurvBlock - 1) / kCurvBlock));
     const dim3 dense(kDenseBlocks);
+    const long cap = list_cap(N);
     unsigned *count = (unsigned *)work;
-    uint32_t *list = (uint32_t *)((char *)work + 256);
+    uint32_t *list = (uint32_t *)((char *)work + (size_t)kLists * kCtrStride * sizeof(unsigned));
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, count);
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(256), 0, st, count);
     if (precision == EBIT_FP64) {
         hipLaunchKernelGGL(k_curv_scan<double>, grid, dim3(kCurvBlock), 0, st, (const double *)C, N, (double *)kappa,
-                           status, list, count);
+                           status, list, count, cap);
         hipLaunchKernelGGL(k_curv_hf<double>, dense, dim3(kCurvBlock), 0, st, (const double *)C, n, (double *)kappa,
-                           status, (const uint32_t *)list, (const unsigned *)count);
+                           status, (const uint32_t *)list, (const unsigned *)count, cap);
         hipLaunchKernelGGL(k_curv_fill<double>, dense, dim3(kCurvBlock), 0, st, n, (double *)kappa, status,
-                           (const uint32_t *)list, (const unsigned *)count);
+                           (const uint32_t *)list, (const unsigned *)count, cap);
     } else {
         hipLaunchKernelGGL(k_curv_scan<float>, grid, dim3(kCurvBlock), 0, st, (const float *)C, N, (float *)kappa,
-                           status, list, count);
+                           status, list, count, cap);
         hipLaunchKernelGGL(k_curv_hf<float>, dense, dim3(kCurvBlock), 0, st, (const float *)C, n, (float *)kappa,
-                           status, (const uint32_t *)list, (const unsigned *)count);
+                           status, (const uint32_t *)list, (const unsigned *)count, cap);
         hipLaunchKernelGGL(k_curv_fill<float>, dense, dim3(kCurvBlock), 0, st, n, (float *)kappa, status,
-                           (const uint32_t *)list, (const unsigned *)count);
+                           (const uint32_t *)list, (const unsigned *)count, cap);
     }
     return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_EHIP;
 }

@@ -1602,70 +1602,114 @@ __device__ __forceinline__ void put_features(__bf16 *row, const uint8_t f[8], co
 
 // Front2VOF phase B with the learned surrogate: unambiguous interfacial cells
 // take the network's volume fraction, computed on matrix cores 16 cells at a
-// time; ambiguous ones fall back to the geometric construction.  One wave per
-// interfacial-cell segment; the block's eight waves share the weights in LDS
-// (124 KB per block: two waves per SIMD).
+// time; ambiguous ones fall back to the geometric construction.  The
+// interfacial-cell segments of the classify pass are taken as one array (a
+// prefix sum of their lengths in LDS), 64 cells per wave at a time, so short
+// segments do not leave tiles empty; the block's waves share the weights in
+// LDS (a block without cells does not copy them).
 template <typename T>
 __global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a)
 {
     using namespace ebit_mlp;
+    constexpr int kThreads = 64 * kSurrWaves;
+    constexpr int kPer = (kMaxWaves + kThreads - 1) / kThreads;
     __shared__ MlpWeights W;
     __shared__ __bf16 xs[kSurrWaves][64 * kRow1];
     __shared__ __bf16 h1s[kSurrWaves][16 * kRow2];
     __shared__ uint32_t rows[kSurrWaves][64];
-    copy_to_lds(&W, &a.w.simg->W, (int)sizeof(MlpWeights));
-    __syncthreads();
+    __shared__ uint32_t pre[kMaxWaves + 1];
+    __shared__ uint32_t wtot[kSurrWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
     const int nc = a.g.nw;
-    for (int ch = blockIdx.x * kSurrWaves + wave; ch < nc; ch += gridDim.x * kSurrWaves) {
-        const uint32_t count = min(a.w.ccnt[ch], (uint32_t)a.g.segcap);
-        int ambc = 0;
-        for (uint32_t base = 0; base < count; base += 64) {
-            const uint32_t i = base + lane;
-            const bool valid = i < count;
-            long q = 0;
-            uint8_t f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            T sv[12];
-            int has = 0, amb = 0;
-            if (valid) {
-                q = (long)a.w.ctask[(size_t)ch * a.g.segcap + i];
-                has = load_cell<T>(a, q, f, sv);
-                amb = cell_ambiguous(f, has);
-            }
-            if (valid && amb) {
-                int am = 0;
-                a.C[q] = cell_volume<T>(f, has, sv, am);
-                ambc += 1;
-            }
-            const bool sur = valid && !amb;
-            const unsigned long long bal = __ballot(sur);
-            const int nsur = __popcll(bal);
-            if (sur) {
-                const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-                put_features<T>(&xs[wave][pos * kRow1], f, sv);
-                rows[wave][pos] = (uint32_t)q;
-            }
-            wave_sync();
-            for (int t0 = 0; t0 < nsur; t0 += 16) {
-                const int rrow = t0 + lr;
-                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (rrow < nsur) v = *(const u16x8 *)&xs[wave][rrow * kRow1 + 8 * lg];
-                float out[4];
-                forward_tile(W, h1s[wave], __builtin_bit_cast(bf16x8, v), out, nullptr, nullptr);
-                if (lr == 0) {
+    const uint32_t segcap = (uint32_t)a.g.segcap;
+    // exclusive prefix of the segment lengths: pre[k] = cells before segment k
+    {
+        uint32_t v[kPer], sum = 0;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int rr = t0 + 4 * lg + r;
-                        if (rr < nsur) a.C[rows[wave][rr]] = (T)out[r];
-                    }
+        for (int j = 0; j < kPer; ++j) {
+            const int k = (int)threadIdx.x * kPer + j;
+            v[j] = k < nc ? min(a.w.ccnt[k], segcap) : 0u;
+            sum += v[j];
+        }
+        const uint32_t incl = wave_incl_scan(sum);
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int w = 0; w < wave; ++w) run += wtot[w];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = (int)threadIdx.x * kPer + j;
+            if (k < nc) pre[k] = run;
+            run += v[j];
+        }
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kSurrWaves; ++w) tot += wtot[w];
+            pre[nc] = tot;
+        }
+        __syncthreads();
+    }
+    const uint32_t total = pre[nc];
+    const uint32_t nchunks = (total + 63) / 64;
+    const uint32_t gw = gridDim.x * kSurrWaves, gwv = blockIdx.x * kSurrWaves + wave;
+    // the ambiguous-cell slots: one per wave of this grid, the rest zero
+    if (blockIdx.x == 0)
+        for (int k = (int)gw + (int)threadIdx.x; k < nc; k += kThreads) a.w.cs[CS_AMB * nc + k] = 0ull;
+    if (blockIdx.x * kSurrWaves < nchunks) copy_to_lds(&W, &a.w.simg->W, (int)sizeof(MlpWeights));
+    __syncthreads();
+    int ambc = 0;
+    for (uint32_t chunk = gwv; chunk < nchunks; chunk += gw) {
+        const uint32_t i = chunk * 64 + (uint32_t)lane;
+        const bool valid = i < total;
+        long q = 0;
+        uint8_t f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        T sv[12];
+        int has = 0, amb = 0;
+        if (valid) {
+            // segment of cell i: the last k with pre[k] <= i
+            int lo = 0, hi = nc;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            q = (long)a.w.ctask[(size_t)lo * a.g.segcap + (i - pre[lo])];
+            has = load_cell<T>(a, q, f, sv);
+            amb = cell_ambiguous(f, has);
+        }
+        if (valid && amb) {
+            int am = 0;
+            a.C[q] = cell_volume<T>(f, has, sv, am);
+            ambc += 1;
+        }
+        const bool sur = valid && !amb;
+        const unsigned long long bal = __ballot(sur);
+        const int nsur = __popcll(bal);
+        if (sur) {
+            const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+            put_features<T>(&xs[wave][pos * kRow1], f, sv);
+            rows[wave][pos] = (uint32_t)q;
+        }
+        wave_sync();
+        for (int t0 = 0; t0 < nsur; t0 += 16) {
+            const int rrow = t0 + lr;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (rrow < nsur) v = *(const u16x8 *)&xs[wave][rrow * kRow1 + 8 * lg];
+            float out[4];
+            forward_tile(W, h1s[wave], __builtin_bit_cast(bf16x8, v), out, nullptr, nullptr);
+            if (lr == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = t0 + 4 * lg + r;
+                    if (rr < nsur) a.C[rows[wave][rr]] = (T)out[r];
                 }
             }
-            wave_sync();
         }
-        const int sa = wave_sum(ambc);
-        if (lane == 0) a.w.cs[CS_AMB * nc + ch] = (unsigned long long)sa;
+        wave_sync();
     }
+    const int sa = wave_sum(ambc);
+    if (lane == 0 && (int)gwv < nc) a.w.cs[CS_AMB * nc + gwv] = (unsigned long long)sa;
 }
 
 // the surrogate's weights image from its FP32 parameters

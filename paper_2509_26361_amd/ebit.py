@@ -101,7 +101,9 @@ def lib():
         L.ebit_curvature.restype = ctypes.c_int
         L.ebit_csf.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_double, P, P]
         L.ebit_csf.restype = ctypes.c_int
-        L.ebit_refine_band.argtypes = [ctypes.c_int32, P, P, P, P, P, P]
+        L.ebit_refine_work_bytes.argtypes = [ctypes.c_int32]
+        L.ebit_refine_work_bytes.restype = ctypes.c_size_t
+        L.ebit_refine_band.argtypes = [ctypes.c_int32, P, P, P, P, P, P, ctypes.c_size_t, P]
         L.ebit_refine_band.restype = ctypes.c_int
         L.ebit_current.argtypes = [P]
         L.ebit_current.restype = ctypes.c_int
@@ -352,15 +354,19 @@ def csf(C, kappa, status, sigma, F=None, stream=None):
     return F
 
 
-def refine_band(flags, mask_prev=None, stream=None):
+def refine_band(flags, mask_prev=None, out=None, stream=None):
     """(mask, bricks, counts[interfacial, masked, bricks, escaped]) of a
-    state's flags (ebit_refine_band); counts is a device int64 tensor."""
+    state's flags (ebit_refine_band); counts is a device int64 tensor.
+    `out`: the (mask, bricks, counts, work) tensors of an earlier call to
+    reuse."""
     n = flags.shape[0]
-    mask = torch.empty_like(flags)
-    bricks = torch.empty((n // 4,) * 3, dtype=torch.uint8, device=flags.device)
-    counts = torch.empty(4, dtype=torch.int64, device=flags.device)
+    if out is None:
+        out = (torch.empty_like(flags), torch.empty((n // 4,) * 3, dtype=torch.uint8, device=flags.device),
+               torch.empty(4, dtype=torch.int64, device=flags.device),
+               torch.empty(lib().ebit_refine_work_bytes(n), dtype=torch.uint8, device=flags.device))
+    mask, bricks, counts, work = out
     rc = lib().ebit_refine_band(n, _ptr(flags), _ptr(mask_prev), _ptr(mask), _ptr(bricks), _ptr(counts),
-                                _stream(stream))
+                                _ptr(work), work.numel(), _stream(stream))
     if rc != EBIT_OK:
         raise EbitError(rc, "ebit_refine_band")
     return mask, bricks, counts
