@@ -1,7 +1,9 @@
 """The refinement band (ebit_refine_band) against its oracle
 (oracle/refine.py): mask, bricks and counts bit-exact on random and sphere
-states, a ragged grid (the last tile along x half empty), the escape count
-after steps, and the 256^3 benchmark state and the 512^3 mixed state."""
+states; small grids, where a tile's staged x words wrap around the grid more
+than once (n < 36), and grids whose last tile is partial along x, y and z
+(the kernel's tiles are 32 x 8 x 8 cells); the escape count after steps, and
+the 256^3 benchmark state and the 512^3 mixed state."""
 import numpy as np
 import pytest
 import torch
@@ -35,7 +37,7 @@ def check(flags_np, prev_np=None):
     return wm
 
 
-@pytest.mark.parametrize("n", [32, 36, 64])
+@pytest.mark.parametrize("n", [8, 12, 20, 28, 32, 36, 44, 64])
 def test_random_states(n):
     check(O.init(I.random_shape(n, n), exact=True).flags)
 
