@@ -49,20 +49,35 @@ struct Grid {
     __device__ __forceinline__ double at3(const int p[3]) const { return at(p[0], p[1], p[2]); }
 };
 
-// Youngs' gradient component along d: weights (1,2,1) x (1,2,1) over the
-// 3x3 cells across d (a on the lower other axis, outer; b inner)
+// The 3x3x3 block of C around p, nb[dz + 1][dy + 1][dx + 1]: every cell the
+// three Youngs gradients read, loaded in one round (27 loads issued together)
 template <typename T>
-__device__ __forceinline__ double youngs(const Grid<T> &g, const int p[3], int d)
+__device__ __forceinline__ void block3(const Grid<T> &g, const int p[3], double nb[3][3][3])
+{
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) nb[dz + 1][dy + 1][dx + 1] = g.at(p[0] + dx, p[1] + dy, p[2] + dz);
+}
+
+// Youngs' gradient component along d from the block: weights (1,2,1) x
+// (1,2,1) over the 3x3 cells across d (a on the lower other axis, outer; b
+// inner)
+__device__ __forceinline__ double youngs(const double nb[3][3][3], int d)
 {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     double acc = 0.0;
+#pragma unroll
     for (int a = -1; a <= 1; ++a)
+#pragma unroll
         for (int b = -1; b <= 1; ++b) {
             const double w = (double)((2 - abs(a)) * (2 - abs(b)));
-            int up[3] = {p[0], p[1], p[2]}, dn[3] = {p[0], p[1], p[2]};
+            int up[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
             up[t1] += a; up[t2] += b; up[d] += 1;
             dn[t1] += a; dn[t2] += b; dn[d] -= 1;
-            acc += w * (g.at3(up) - g.at3(dn));
+            acc += w * (nb[up[2] + 1][up[1] + 1][up[0] + 1] - nb[dn[2] + 1][dn[1] + 1][dn[0] + 1]);
         }
     return acc;
 }
@@ -190,6 +205,16 @@ struct ListRange {
 };
 static_assert(kCurvBlock == kLists, "one thread per sub-list counter in ListRange::build");
 
+// Item i of the dense passes for this thread: the listed cells go in chunks
+// of 64 (one wave), chunk c to wave c / G of workgroup c % G, so that a few
+// tens of thousands of cells spread over every CU rather than filling the
+// first workgroups (each lane gathers a 3x3x7 stencil: the texture units of
+// the CUs that hold the cells are the limit).  A bijection of [0, 4 G 64).
+__device__ __forceinline__ uint32_t dense_first()
+{
+    return (((uint32_t)threadIdx.x >> 6) * gridDim.x + blockIdx.x) * 64u + ((uint32_t)threadIdx.x & 63u);
+}
+
 // pass 2 (dense over the list, one lane per interfacial cell): height-function
 // curvature (status 1 or 2); status 4 stays where no direction has 9 valid
 // columns
@@ -203,11 +228,16 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_hf(const T *__restrict__ C,
     lr.build(count, wtot);
     const Grid<T> g{C, n};
     const double h = 1.0 / (double)n;
-    for (uint32_t i = blockIdx.x * kCurvBlock + threadIdx.x; i < lr.total(); i += gridDim.x * kCurvBlock) {
+    for (uint32_t i = dense_first(); i < lr.total(); i += gridDim.x * kCurvBlock) {
         const long q = lr.cell(list, cap, i);
         const int p[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / ((long)n * n))};
         double gd[3];
-        for (int d = 0; d < 3; ++d) gd[d] = fabs(youngs(g, p, d));
+        {
+            double nb[3][3][3];
+            block3(g, p, nb);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gd[d] = fabs(youngs(nb, d));
+        }
         // candidate order: decreasing |g_d|, ties by lower axis
         int ord[3] = {0, 1, 2};
         for (int a = 1; a < 3; ++a)
@@ -236,24 +266,32 @@ __global__ __launch_bounds__(kCurvBlock) void k_curv_fill(int n, T *__restrict__
     __shared__ uint32_t pre[kLists + 1], wtot[kCurvBlock / 64];
     ListRange lr{pre};
     lr.build(count, wtot);
-    for (uint32_t i = blockIdx.x * kCurvBlock + threadIdx.x; i < lr.total(); i += gridDim.x * kCurvBlock) {
+    for (uint32_t i = dense_first(); i < lr.total(); i += gridDim.x * kCurvBlock) {
         const long q = lr.cell(list, cap, i);
         if (status[q] != KS_MISSING) continue;
         const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / ((long)n * n));
+        // the 26 statuses in one round, then the curvatures of the valid
+        // neighbours in another, summed in [dz][dy][dx] order
+        long r[27];
+        uint8_t t[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+            r[k] = (long)wrapc(x + dx, n) + (long)n * ((long)wrapc(y + dy, n) + (long)n * (long)wrapc(z + dz, n));
+        }
+#pragma unroll
+        for (int k = 0; k < 27; ++k) t[k] = k == 13 ? (uint8_t)KS_NONE : status[r[k]];
+        double kv[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) kv[k] = (t[k] == KS_HF || t[k] == KS_HF_OTHER) ? (double)kap[r[k]] : 0.0;
         double s = 0.0;
         int cnt = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0 && dz == 0) continue;
-                    const long r = (long)wrapc(x + dx, n) +
-                                   (long)n * ((long)wrapc(y + dy, n) + (long)n * (long)wrapc(z + dz, n));
-                    const uint8_t t = status[r];
-                    if (t == KS_HF || t == KS_HF_OTHER) {
-                        s += (double)kap[r];
-                        ++cnt;
-                    }
-                }
+#pragma unroll
+        for (int k = 0; k < 27; ++k)
+            if (t[k] == KS_HF || t[k] == KS_HF_OTHER) {
+                s += kv[k];
+                ++cnt;
+            }
         if (cnt) {
             kap[q] = (T)(s / (double)cnt);
             status[q] = KS_MEAN;
