@@ -68,9 +68,12 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint32_t w)
     return w & kOnes;
 }
 
-// Persistent workgroups: workgroup b takes tiles b, b + G, ... (x fastest, so
-// the workgroups running together work on neighbouring tiles and share their
-// halo rows in L2).  The node words of the next tile are loaded while the
+// Persistent workgroups, XCD-aware: workgroup ids are dealt to the eight XCDs
+// round robin, so the workgroups b = x mod 8 (one XCD) take the x-th eighth
+// of the tiles (x fastest, then y, then z: a slab along z), workgroup j of
+// them the tiles j, j + Gx, ... of it.  The workgroups of an XCD running
+// together work on neighbouring tiles of their slab and find their halo rows
+// in that XCD's L2.  The node words of the next tile are loaded while the
 // current one is computed; counts are summed over the workgroup's tiles and
 // added to its set once.  The thread's coordinates in the staging and in the
 // three LDS passes are the same for every tile and are computed once.
@@ -133,15 +136,19 @@ __global__ __launch_bounds__(kThreads) void k_refine(int n, const uint8_t *__res
         dsrc[i] = (rz * RY + ry) * IW + j;
     }
     uint32_t c_int = 0, c_mask = 0, c_brick = 0, c_esc = 0;
-    const int G = (int)gridDim.x;
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nx = G < 8 ? G : 8, x = b % nx, j0 = b / nx;
+    const int Gx = (G - x + nx - 1) / nx;                 // workgroups b' < G with b' = x mod nx
+    const int per = (ntiles + nx - 1) / nx;
+    const int t0 = x * per, t1 = min(t0 + per, ntiles);  // this XCD's tiles
 #pragma unroll
     for (int sl = 0; sl < kAhead; ++sl)
-        if ((int)blockIdx.x + sl * G < ntiles) load_tile((int)blockIdx.x + sl * G, v[sl]);
-    for (int base = blockIdx.x; base < ntiles; base += kAhead * G)
+        if (t0 + j0 + sl * Gx < t1) load_tile(t0 + j0 + sl * Gx, v[sl]);
+    for (int base = t0 + j0; base < t1; base += kAhead * Gx)
 #pragma unroll
     for (int sl = 0; sl < kAhead; ++sl) {
-        const int tile = base + sl * G;
-        if (tile >= ntiles) break;
+        const int tile = base + sl * Gx;
+        if (tile >= t1) break;
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_refine(int n, const uint8_t *__res
         }
         if (t < BZ * BY * WX) (&bword[0][0][0])[t] = 0;
         __syncthreads();
-        if (tile + kAhead * G < ntiles) load_tile(tile + kAhead * G, v[sl]);
+        if (tile + kAhead * Gx < t1) load_tile(tile + kAhead * Gx, v[sl]);
         // interfacial bytes: cell c has a marker on one of its 12 edges -- x-edges
         // (bit 4) at nodes c + (0, a, b), y-edges (bit 5) at c + (a, 0, b), z-edges
         // (bit 6) at c + (a, b, 0), a, b in {0, 1}
