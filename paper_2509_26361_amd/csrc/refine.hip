@@ -3,17 +3,18 @@
 // level, and a Courant number of at most one keeps the interface inside that
 // region for the next step).
 //
-// One streaming pass over the periodic n^3 grid.  A workgroup owns a tile of
-// 32 x 8 x 8 cells and stages the flags of the nodes around it in LDS; from
-// there everything runs on 32-bit words that hold four consecutive cells (one
-// byte each, 0 or 1): the interfacial bytes of the 36 cell rows around the
-// tile, the OR along x by byte shifts across word boundaries, then along y and
-// z by ORing whole words of neighbouring rows.  A 4^3 brick is one word wide,
-// so the brick flags are ORs of words, and the counts are popcounts of words.
-// The mask is written as whole words.  The tile's halo (one node row below,
-// two above, along y and z) is (11/8)^2 of its rows, so about 2 bytes are
-// read and 1 written per cell: HBM bound.  The last tile along y and z may
-// reach past n (n is a multiple of 4): its cells beyond n are not written.
+// One pass over the periodic n^3 grid in tiles of 32 x 8 x 8 cells, taken in
+// turn by persistent workgroups (see k_refine).  A tile's node flags are
+// staged in LDS as 32-bit words; from there everything runs on words that
+// hold four consecutive cells (one byte each, 0 or 1): the interfacial bytes
+// of the 100 cell rows around the tile, the OR along x by byte shifts across
+// word boundaries, then along y and z by ORing whole words of neighbouring
+// rows.  A 4^3 brick is one word wide, so the brick flags are ORs of words,
+// and the counts are popcounts of words.  The mask is written as whole words.
+// About 1 byte is read (the halo rows come from L2) and 1 written per cell;
+// the four LDS passes and their barriers per tile, not HBM, set the time.
+// The last tile along y and z may reach past n (n is a multiple of 4): its
+// cells beyond n are not written.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
