@@ -886,6 +886,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             ++nact;
             const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
             const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
+            // the lane's node in the buffer this sweep writes: its markers say
+            // where that buffer holds fractions other than zero (loaded here,
+            // used by the stores below)
+            const uint8_t fo = a.flo[qs];
             const uint8_t *tf = tfl[j];
             const double *tx = txd[j];
             auto ncol = [&](int di, int d1, int d2) { return (tf[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
@@ -945,9 +949,18 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             if (!same && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
             // unchanged now and by the previous sweep: both buffers hold it already
             if (!(same && !a.full && lastj + 2 <= t)) {
-                a.so[D][qs] = sdn;
-                if (!task[0]) a.so[A1][qs] = T(0);
-                if (!task[1]) a.so[A2][qs] = T(0);
+                // a row of fractions (four lanes, 32 or 16 bytes) is written only
+                // if one of its edges holds a marker now or in the buffer written
+                // (elsewhere that buffer already holds the zeros); whole rows, so
+                // that no store covers part of a row
+                const uint32_t mk = (uint32_t)(out | fo);
+                const unsigned long long rD = __ballot(((mk >> (4 + D)) & 1) != 0);
+                const unsigned long long r1 = __ballot(((mk >> (4 + A1)) & 1) != 0);
+                const unsigned long long r2 = __ballot(((mk >> (4 + A2)) & 1) != 0);
+                const int row = lane & ~3;
+                if ((rD >> row) & 15ull) a.so[D][qs] = sdn;
+                if (!task[0] && ((r1 >> row) & 15ull)) a.so[A1][qs] = T(0);
+                if (!task[1] && ((r2 >> row) & 15ull)) a.so[A2][qs] = T(0);
                 if (!fnode) a.flo[qs] = out;
             }
             // queue: unaligned markers of both planes, then the face nodes and their faces
