@@ -162,6 +162,10 @@ struct Work {
     double *epart;       // 6 * kRedBlocks partials of the error sums (ebit_errors), then the 6 totals
     ebit_mlp::MlpImage *simg;   // the surrogate's weights in the layout its kernel stages in LDS
     uint32_t *ocnt;      // [kOrderBlocks] band-ordering counts / offsets
+    // rmask[buf][b]: the rows of brick b (16 rows of four nodes, y + 4 z) that
+    // may hold a marker in state buffer buf, 16 bits per edge family x, y, z;
+    // exact for a brick the last sweep into buf wrote, all ones after ebit_init
+    unsigned long long *rmask[2];
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -193,6 +197,7 @@ size_t work_layout(int n, Work *w, char *base)
     p = take(6 * (kRedBlocks + 1) * sizeof(double)); if (w) w->epart = (double *)p;
     p = take(sizeof(ebit_mlp::MlpImage)); if (w) w->simg = (ebit_mlp::MlpImage *)p;
     p = take(kOrderBlocks * 4); if (w) w->ocnt = (uint32_t *)p;
+    for (int k = 0; k < 2; ++k) { p = take(nb * 8); if (w) w->rmask[k] = (unsigned long long *)p; }
     return off;
 }
 
@@ -210,6 +215,20 @@ __device__ __forceinline__ uint32_t bpack_lin(int b, int nb1) { return bpack(b %
 __device__ __forceinline__ uint32_t brick_shift(uint32_t p, int nb1, int dx, int dy, int dz)
 {
     return bpack(wrp(bx_of(p) + dx, nb1), wrp(by_of(p) + dy, nb1), wrp(bz_of(p) + dz, nb1));
+}
+
+// the rows (four consecutive lanes each) of a ballot that hold a set bit, as
+// 16 bits: bit r for lanes 4 r .. 4 r + 3
+__device__ __forceinline__ uint32_t rows16(unsigned long long b)
+{
+    b |= b >> 1;
+    b |= b >> 2;
+    b &= 0x1111111111111111ull;        // bit 4 r: row r
+    b = (b | (b >> 3)) & 0x0303030303030303ull;
+    b = (b | (b >> 6)) & 0x000F000F000F000Full;
+    b = (b | (b >> 12)) & 0x000000FF000000FFull;
+    b = (b | (b >> 24)) & 0xFFFFull;
+    return (uint32_t)b;
 }
 
 // sum of a per-lane value over the wave (result valid in every lane)
@@ -549,6 +568,8 @@ __global__ void k_zero_work(Work w, Geo g)
         w.fmark[i] = 0;
         w.bcnt[i] = 0;
         w.bchg[i] = 0;
+        w.rmask[0][i] = ~0ull;
+        w.rmask[1][i] = ~0ull;
     }
     if (i < 4 * kNum) w.bnum[i * kPad] = 0;
     if (i < 3 * kNum) w.fnum[i * kPad] = 0;
@@ -570,6 +591,7 @@ struct SweepArgs {
     const T *s[3];
     uint8_t *flo;
     T *so[3];
+    unsigned long long *rmo;   // row masks of the buffer written (Work::rmask)
     const T *U;
     T c;              // (dt n) g
     Work w;
@@ -886,10 +908,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             ++nact;
             const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
             const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
-            // the lane's node in the buffer this sweep writes: its markers say
-            // where that buffer holds fractions other than zero (loaded here,
-            // used by the stores below)
-            const uint8_t fo = a.flo[qs];
+            // the rows of the brick that may hold markers in the buffer this
+            // sweep writes (loaded here, used by the stores below)
+            const unsigned long long om = a.rmo[blin((uint32_t)b, nb1)];
             const uint8_t *tf = tfl[j];
             const double *tx = txd[j];
             auto ncol = [&](int di, int d1, int d2) { return (tf[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
@@ -950,18 +971,18 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             // unchanged now and by the previous sweep: both buffers hold it already
             if (!(same && !a.full && lastj + 2 <= t)) {
                 // a row of fractions (four lanes, 32 or 16 bytes) is written only
-                // if one of its edges holds a marker now or in the buffer written
-                // (elsewhere that buffer already holds the zeros); whole rows, so
-                // that no store covers part of a row
-                const uint32_t mk = (uint32_t)(out | fo);
-                const unsigned long long rD = __ballot(((mk >> (4 + D)) & 1) != 0);
-                const unsigned long long r1 = __ballot(((mk >> (4 + A1)) & 1) != 0);
-                const unsigned long long r2 = __ballot(((mk >> (4 + A2)) & 1) != 0);
-                const int row = lane & ~3;
-                if ((rD >> row) & 15ull) a.so[D][qs] = sdn;
-                if (!task[0] && ((r1 >> row) & 15ull)) a.so[A1][qs] = T(0);
-                if (!task[1] && ((r2 >> row) & 15ull)) a.so[A2][qs] = T(0);
+                // if one of its edges holds a marker now or may hold one in the
+                // buffer written (elsewhere that buffer already holds the zeros);
+                // whole rows, so that no store covers part of a row
+                const unsigned long long nm = ((unsigned long long)rows16(__ballot(((out >> (4 + D)) & 1) != 0)) << (16 * D)) |
+                                              ((unsigned long long)rows16(__ballot(task[0])) << (16 * A1)) |
+                                              ((unsigned long long)rows16(__ballot(task[1])) << (16 * A2));
+                const unsigned long long wm = (nm | om) >> (lane >> 2);
+                if ((wm >> (16 * D)) & 1) a.so[D][qs] = sdn;
+                if (!task[0] && ((wm >> (16 * A1)) & 1)) a.so[A1][qs] = T(0);
+                if (!task[1] && ((wm >> (16 * A2)) & 1)) a.so[A2][qs] = T(0);
                 if (!fnode) a.flo[qs] = out;
+                if (lane == 0) a.rmo[blin((uint32_t)b, nb1)] = nm;
             }
             // queue: unaligned markers of both planes, then the face nodes and their faces
             {
@@ -2007,6 +2028,7 @@ SweepArgs<T> sweep_args(const ebit_ctx *c, const void *U, T cf)
     a.g = c->g;
     a.fl = c->flags[c->cur];
     a.flo = c->flags[c->cur ^ 1];
+    a.rmo = c->w.rmask[c->cur ^ 1];
     for (int e = 0; e < 3; ++e) {
         a.s[e] = (const T *)c->s[c->cur][e];
         a.so[e] = (T *)c->s[c->cur ^ 1][e];
