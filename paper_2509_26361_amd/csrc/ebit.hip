@@ -164,7 +164,8 @@ struct Work {
     uint32_t *ocnt;      // [kOrderBlocks] band-ordering counts / offsets
     // rmask[buf][b]: the rows of brick b (16 rows of four nodes, y + 4 z) that
     // may hold a marker in state buffer buf, 16 bits per edge family x, y, z;
-    // exact for a brick the last sweep into buf wrote, all ones after ebit_init
+    // exact where a sweep over a brick-ordered list wrote the brick last, all
+    // ones after ebit_init and where a sweep over a claim-ordered list did
     unsigned long long *rmask[2];
 };
 
@@ -580,6 +581,15 @@ __global__ void k_zero_work(Work w, Geo g)
     if (i < ST_COUNT) w.stat[i] = 0;
 }
 
+// every row of every brick may hold a marker, in both buffers (Work::rmask)
+__global__ __launch_bounds__(256) void k_rmask_ones(Work w, Geo g)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < g.nb; i += (long)gridDim.x * blockDim.x) {
+        w.rmask[0][i] = ~0ull;
+        w.rmask[1][i] = ~0ull;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a1-a4: one sweep along axis D (secs. 2.1-2.4)
 // ---------------------------------------------------------------------------
@@ -908,9 +918,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             ++nact;
             const int org[3] = {bx_of((uint32_t)b) * 4, by_of((uint32_t)b) * 4, bz_of((uint32_t)b) * 4};
             const long qs = (long)(org[0] + lu[0]) + str[1] * (org[1] + lu[1]) + str[2] * (org[2] + lu[2]);
-            // the rows of the brick that may hold markers in the buffer this
-            // sweep writes (loaded here, used by the stores below)
-            const unsigned long long om = a.rmo[blin((uint32_t)b, nb1)];
+            // RUN: the rows of the brick that may hold markers in the buffer
+            // this sweep writes (loaded here, used by the stores below)
+            const unsigned long long om = RUN ? a.rmo[blin((uint32_t)b, nb1)] : 0ull;
             const uint8_t *tf = tfl[j];
             const double *tx = txd[j];
             auto ncol = [&](int di, int d1, int d2) { return (tf[tself + di + kAD * (d1 + kAA * d2)] >> 7) & 1; };
@@ -970,19 +980,30 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             if (!same && lane == 0) a.w.bchg[blin((uint32_t)b, nb1)] = t;
             // unchanged now and by the previous sweep: both buffers hold it already
             if (!(same && !a.full && lastj + 2 <= t)) {
-                // a row of fractions (four lanes, 32 or 16 bytes) is written only
-                // if one of its edges holds a marker now or may hold one in the
-                // buffer written (elsewhere that buffer already holds the zeros);
-                // whole rows, so that no store covers part of a row
-                const unsigned long long nm = ((unsigned long long)rows16(__ballot(((out >> (4 + D)) & 1) != 0)) << (16 * D)) |
-                                              ((unsigned long long)rows16(__ballot(task[0])) << (16 * A1)) |
-                                              ((unsigned long long)rows16(__ballot(task[1])) << (16 * A2));
-                const unsigned long long wm = (nm | om) >> (lane >> 2);
-                if ((wm >> (16 * D)) & 1) a.so[D][qs] = sdn;
-                if (!task[0] && ((wm >> (16 * A1)) & 1)) a.so[A1][qs] = T(0);
-                if (!task[1] && ((wm >> (16 * A2)) & 1)) a.so[A2][qs] = T(0);
+                if (RUN) {
+                    // a row of fractions (four lanes, 32 or 16 bytes) is written
+                    // only if one of its edges holds a marker now or may hold one
+                    // in the buffer written (elsewhere that buffer already holds
+                    // the zeros); whole rows, so that no store covers part of a
+                    // row.  This saves HBM writes on large bands; on small grids,
+                    // bound by the waves' chains of rounds, the plain stores
+                    // below are faster.
+                    const unsigned long long nm =
+                        ((unsigned long long)rows16(__ballot(((out >> (4 + D)) & 1) != 0)) << (16 * D)) |
+                        ((unsigned long long)rows16(__ballot(task[0])) << (16 * A1)) |
+                        ((unsigned long long)rows16(__ballot(task[1])) << (16 * A2));
+                    const unsigned long long wm = (nm | om) >> (lane >> 2);
+                    if ((wm >> (16 * D)) & 1) a.so[D][qs] = sdn;
+                    if (!task[0] && ((wm >> (16 * A1)) & 1)) a.so[A1][qs] = T(0);
+                    if (!task[1] && ((wm >> (16 * A2)) & 1)) a.so[A2][qs] = T(0);
+                    if (lane == 0) a.rmo[blin((uint32_t)b, nb1)] = nm;
+                } else {
+                    // (the row masks are left stale: rmask_before_sweep)
+                    a.so[D][qs] = sdn;
+                    if (!task[0]) a.so[A1][qs] = T(0);
+                    if (!task[1]) a.so[A2][qs] = T(0);
+                }
                 if (!fnode) a.flo[qs] = out;
-                if (lane == 0) a.rmo[blin((uint32_t)b, nb1)] = nm;
             }
             // queue: unaligned markers of both planes, then the face nodes and their faces
             {
@@ -1974,6 +1995,7 @@ struct ebit_ctx {
     int fuse;              // ebit_advance launches a Front2VOF with the next x sweep
     int order;             // each sweep's band list is put in brick order first
     int next_dir;          // axis of the sweep after the one being launched, -1 if not known
+    int rm_dirty;          // a sweep over a claim-ordered list left Work::rmask stale
     int timing;            // bracket every timing-th launch of each kind with events (0: off)
     unsigned tseen[3];     // launches of each kind since timing was switched on
     int tsel;              // the current launch is bracketed
@@ -2077,11 +2099,25 @@ void order_revisit(const ebit_ctx *c, uint32_t gen, int full, hipStream_t st)
     order_list(c, c->w.fmark, gen, c->w.flist[gen % 3], c->w.fnum + (gen % 3) * kNum * kPad, st);
 }
 
+// Row masks (Work::rmask) before a sweep: kept by sweeps over brick-ordered
+// lists, which read them; a sweep over a claim-ordered list neither reads nor
+// updates them, so the next brick-ordered one first sets them all to ones.
+void rmask_before_sweep(ebit_ctx *c, int run, hipStream_t st)
+{
+    if (!run) {
+        c->rm_dirty = 1;
+    } else if (c->rm_dirty) {
+        hipLaunchKernelGGL(k_rmask_ones, dim3(clampi((c->g.nb + 255) / 256, 4096)), dim3(256), 0, st, c->w, c->g);
+        c->rm_dirty = 0;
+    }
+}
+
 template <typename T, int D>
 void launch_sweep(ebit_ctx *c, const void *U, T cf, hipStream_t st)
 {
     order_band(c, st);
     const SweepArgs<T> a = sweep_args<T>(c, U, cf);
+    rmask_before_sweep(c, a.run, st);
     time_begin(c, st, 0);
     if (a.run) hipLaunchKernelGGL((k_sweep<T, D, 1>), dim3(c->g.nw), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_sweep<T, D, 0>), dim3(c->g.nw), dim3(64), 0, st, a);
@@ -2150,6 +2186,7 @@ int f2v_sweep_x_impl(ebit_ctx *c, void *C, const void *Ux, double g, double dt, 
     const SweepArgs<T> a = sweep_args<T>(c, Ux, (T)((dt * (double)c->n) * g));
     order_revisit(c, f.gen, f.full, st);
     order_band(c, st);
+    rmask_before_sweep(c, a.run, st);
     time_begin(c, st, 2);
     const int classify = c->surr ? 1 : 0;
     if (a.run) hipLaunchKernelGGL((k_f2v_sweep_x<T, 1>), dim3(2 * c->g.nw), dim3(64), 0, st, a, f, classify);
@@ -2277,6 +2314,7 @@ int ebit_init(ebit_ctx **out, const ebit_desc *d, const double *phi_nodes, const
     c->fuse = 1;
     c->order = d->n >= EBIT_ORDER_MIN_N;
     c->next_dir = -1;
+    c->rm_dirty = 0;
     hipStream_t st = S(stream);
     long N = (long)d->n * d->n * d->n;
     if (phi_nodes) {
