@@ -640,11 +640,12 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
     for (int base = 0; base < ntask; base += 64) {
         const int i = base + lane;
         if (i < ntask) {
-            const long q = tq[i];
+            const uint32_t pk = tq[i];
             const int ty = tt[i];
             const bool second = ty & 1;             // plane (D, A2)
             const int unal = (ty >> 1) & 1, c00 = (ty >> 2) & 1;
-            const int P[3] = {(int)(q % n), (int)((q / n) % n), (int)(q / nn)};
+            const int P[3] = {(int)(pk & 1023u), (int)((pk >> 10) & 1023u), (int)(pk >> 20)};
+            const uint32_t q = (uint32_t)P[0] + __umul24((uint32_t)P[1], (uint32_t)n) + __umul24((uint32_t)P[2], (uint32_t)nn);
             PlaneTask<T, D, RUN> p;
             p.fl = a.fl;
             p.sD = a.s[D];
@@ -656,7 +657,7 @@ __device__ __forceinline__ void run_tasks(const SweepArgs<T> &a, const uint32_t 
             p.cj = second ? P[A2] : P[A1];
             p.strD = (uint32_t)str[D];
             p.strA = (uint32_t)(second ? str[A2] : str[A1]);
-            p.base = (uint32_t)(second ? (long)P[A1] * str[A1] : (long)P[A2] * str[A2]);
+            p.base = second ? __umul24((uint32_t)P[A1], (uint32_t)str[A1]) : __umul24((uint32_t)P[A2], (uint32_t)str[A2]);
             p.hb = 4 + D;
             p.vb = second ? 4 + A2 : 4 + A1;
             p.fb = second ? 1 + A1 : 1 + A2;
@@ -1007,6 +1008,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
             }
             // queue: unaligned markers of both planes, then the face nodes and their faces
             {
+                // a task's node as packed coordinates x | y << 10 | z << 20
+                const uint32_t tpos = (uint32_t)(org[0] + lu[0]) | ((uint32_t)(org[1] + lu[1]) << 10) |
+                                      ((uint32_t)(org[2] + lu[2]) << 20);
                 const unsigned long long lt = (1ull << lane) - 1ull;
                 unsigned long long bal = __ballot(fnode);
                 const int slot = nslot + __popcll(bal & lt);
@@ -1015,7 +1019,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 bal = __ballot(task[2]);
                 if (task[2]) {
                     const int i = ntask + __popcll(bal & lt);
-                    tq[i] = (uint32_t)qs;
+                    tq[i] = tpos;
                     tt[i] = (uint8_t)(0 | ((int)task[0] << 1) | (c00 << 2));
                     ts[i] = (uint16_t)slot;
                 }
@@ -1023,7 +1027,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                 bal = __ballot(task[3]);
                 if (task[3]) {
                     const int i = ntask + __popcll(bal & lt);
-                    tq[i] = (uint32_t)qs;
+                    tq[i] = tpos;
                     tt[i] = (uint8_t)(1 | ((int)task[1] << 1) | (c00 << 2));
                     ts[i] = (uint16_t)slot;
                 }
