@@ -1634,7 +1634,8 @@ __device__ __forceinline__ int load_cell(const F2VArgs<T> &a, long q, uint8_t f[
 {
     const int n = a.g.n;
     uint32_t qc[8];
-    corner_index(n, a.g.nn, (int)(q % n), (int)((q / n) % n), (int)(q / a.g.nn), qc);
+    const uint32_t uq = (uint32_t)q, un = (uint32_t)n, qn = uq / un;   // n^3 < 2^32: 32-bit division
+    corner_index(n, a.g.nn, (int)(uq - qn * un), (int)(qn % un), (int)(qn / un), qc);
 #pragma unroll
     for (int k = 0; k < 8; ++k) f[k] = a.fl[qc[k]];
     const int has = marker_mask(f);
