@@ -68,7 +68,12 @@ typedef struct {
     size_t scratch_bytes;
 } ebit_desc;
 
-/* Bytes of device scratch the library needs for an n^3 grid. */
+/* Bytes of device scratch the library needs for an n^3 grid.  The scratch
+ * holds the context's work lists and per-brick records of what the state
+ * buffers hold (e.g. which rows of a 4^3 brick may carry a fraction other
+ * than zero); they are built by ebit_init and kept by the library's own
+ * calls, so the state buffers and the scratch must not be written by anyone
+ * else between calls (start again with ebit_init after doing so). */
 size_t ebit_scratch_bytes(int32_t n);
 
 /*
