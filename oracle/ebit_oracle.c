@@ -427,7 +427,8 @@ static int new_face_colour(const plane *P, const uint8_t *cn, int i, int j)
  * state (flags_in, s*_in) and writes the new one (flags_out, s*_out).
  * counters[0] fallbacks (no odd crossing set), [1] edges with >1 crossing,
  * [2] markers with |delta| > 1 (CFL contract broken), [3] aligned edges on
- * which more than one marker landed.
+ * which more than one marker landed, [4] those of them where the markers
+ * annihilated (an even number landed: the end colours agree, no marker).
  * READINGS: node velocity, linear along the marker's own edge (the paper's
  * bilinear interpolation restricted to an edge); delta = (dt n) g u (cell
  * units); time level t^n for all three sweeps; half-open node rule: a point X
@@ -445,7 +446,7 @@ int orc_sweep(int n, int d, double g, double dt, const double *U,
     double *xd = (double *)malloc(sizeof(double) * N);
     double *dv[3] = {NULL, NULL, NULL};
     uint8_t *cn = (uint8_t *)malloc(N);
-    long long cnt[4] = {0, 0, 0, 0};
+    long long cnt[5] = {0, 0, 0, 0, 0};
 
     /* Euler step of every marker (eq. Eq_marker_dis) */
     for (int e = 0; e < 3; e++) if (e != d) dv[e] = (double *)malloc(sizeof(double) * N);
@@ -485,8 +486,8 @@ int orc_sweep(int n, int d, double g, double dt, const double *U,
                 if (bitof(fl[q], 4 + d) && xd[q] < 0.0) col ^= 1;      /* crossed downward */
                 cn[q] = (uint8_t)col;
             }
-    long long nfb = 0, nmerge = 0;
-#pragma omp parallel for reduction(+ : nfb, nmerge)
+    long long nfb = 0, nmerge = 0, nannih = 0;
+#pragma omp parallel for reduction(+ : nfb, nmerge, nannih)
     for (int z = 0; z < n; z++)
         for (int y = 0; y < n; y++)
             for (int x = 0; x < n; x++) {
@@ -517,7 +518,7 @@ int orc_sweep(int n, int d, double g, double dt, const double *U,
                     if (bitof(fl[qm], 4 + d) && xd[qm] >= 1.0) k++;
                     if (bitof(fl[q], 4 + d) && xd[q] >= 0.0 && xd[q] < 1.0) k++;
                     if (bitof(fl[qp], 4 + d) && xd[qp] < 0.0) k++;
-                    if (k >= 2) nmerge++;      /* annihilated pair (sec. 2.2) */
+                    if (k >= 2) { nmerge++; nannih++; }   /* annihilated pair (sec. 2.2) */
                 }
                 /* READING: face colours of the faces normal to d are not updated */
                 out |= (uint8_t)(fl[q] & (1u << (1 + d)));
@@ -526,6 +527,7 @@ int orc_sweep(int n, int d, double g, double dt, const double *U,
 
     cnt[0] += nfb;
     cnt[3] += nmerge;
+    cnt[4] += nannih;
     /* unaligned markers and face colours of the two planes containing d (sec. 2.3) */
     for (int fam = 0; fam < 2; fam++) {
         int a = (d + 1 + fam) % 3;
@@ -555,7 +557,7 @@ int orc_sweep(int n, int d, double g, double dt, const double *U,
         cnt[0] += c0;
         cnt[1] += c1;
     }
-    if (counters) for (int t = 0; t < 4; t++) counters[t] += cnt[t];
+    if (counters) for (int t = 0; t < 5; t++) counters[t] += cnt[t];
     free(xd); free(cn);
     for (int e = 0; e < 3; e++) free(dv[e]);
     return cnt[2] ? 1 : 0;

@@ -119,12 +119,13 @@ def init(shape, exact: bool = False) -> State:
 
 def sweep(st: State, d: int, g: float, dt: float, U, L=None) -> tuple:
     """One advection sweep along axis ``d`` (0, 1, 2); returns (new state,
-    counters[fallback, multi-crossing, cfl, aligned-merges]).  ``L``: a
+    counters[fallback, multi-crossing, cfl, aligned-merges, of which
+    annihilations]).  ``L``: a
     library from build_variant instead of the oracle."""
     n = st.n
     U = _f64(U)
     out = State(n, np.zeros_like(st.flags), [np.zeros_like(x) for x in st.s])
-    cnt = np.zeros(4, np.int64)
+    cnt = np.zeros(5, np.int64)
     (L or lib()).orc_sweep(n, int(d), float(g), float(dt), _p(U), _p(st.flags),
                     _p(st.s[0]), _p(st.s[1]), _p(st.s[2]), _p(out.flags),
                     _p(out.s[0]), _p(out.s[1]), _p(out.s[2]), _p(cnt))
@@ -133,7 +134,7 @@ def sweep(st: State, d: int, g: float, dt: float, U, L=None) -> tuple:
 
 def step(st: State, Uxyz, g: float, dt: float, order=(0, 1, 2)) -> tuple:
     """Three sweeps x, y, z at the same time level (one time step)."""
-    tot = np.zeros(4, np.int64)
+    tot = np.zeros(5, np.int64)
     for d in order:
         st, c = sweep(st, d, g, dt, Uxyz[d])
         tot += c

@@ -22,7 +22,7 @@ def _errors(n, centre, vel, dt, steps, gfun):
     C0, _ = O.f2v(st)
     V0 = sum(O.volume(C0))
     em = 0.0
-    tot = np.zeros(4, np.int64)
+    tot = np.zeros(5, np.int64)
     for s in range(steps):
         st, c = O.step(st, vel, gfun(s, dt), dt)
         tot += c
@@ -131,7 +131,8 @@ def _line_bruteforce(col, pos_exists, pos_s, delta, n):
     """Aligned markers of one periodic line moved by a constant delta:
     colours are pulled back (new colour at node i = old phase at i - delta)
     and markers are binned per edge, an even count annihilating and three
-    leaving the middle one (sec. 2.2)."""
+    leaving the middle one (sec. 2.2).  Also returns the number of edges
+    reached by more than one marker and, of those, by an even number."""
     Xold = [i + pos_s[i] for i in range(n) if pos_exists[i]]
     newcol = np.zeros(n, np.uint8)
     for i in range(n):
@@ -151,23 +152,27 @@ def _line_bruteforce(col, pos_exists, pos_s, delta, n):
         bins.setdefault(k % n, []).append(Xn - k)
     ex = np.zeros(n, bool)
     s = np.zeros(n)
+    merged = sum(1 for v in bins.values() if len(v) > 1)
+    annihilated = sum(1 for v in bins.values() if len(v) > 1 and len(v) % 2 == 0)
     for k, v in bins.items():
         if len(v) % 2 == 1:
             ex[k] = True
             s[k] = sorted(v)[len(v) // 2]
-    return newcol, ex, s
+    return newcol, ex, s, merged, annihilated
 
 
 @pytest.mark.parametrize("seed", range(3))
 def test_aligned_markers_and_colours_bruteforce(seed):
     """Independent per-line recount for a velocity constant along each line
-    (dyadic values so every sum is exact)."""
+    (dyadic values so every sum is exact): colours, markers, and the counts of
+    edges reached by several markers and of annihilated pairs."""
     n = 16
     rng = np.random.default_rng(seed)
     sh = I.random_shape(n, seed + 40)
     col = (sh.phi_nodes > 0).astype(np.uint8)
     s = [np.floor(rng.uniform(0, 1, (n, n, n)) * 2 ** 20) / 2 ** 20 for _ in range(3)]
     st = make_state(col, s)
+    total_annihilated = 0
     for d in range(3):
         f = rng.integers(-1024, 1025, size=(n, n)) / 1024.0
         shape = [n, n, n]
@@ -181,13 +186,19 @@ def test_aligned_markers_and_colours_bruteforce(seed):
         F2 = np.moveaxis(st2.flags, ax, -1)
         S2 = np.moveaxis(st2.s[d], ax, -1)
         Uf = np.moveaxis(U, ax, -1)
+        merged = annihilated = 0
         for a in range(n):
             for b in range(n):
-                newcol, ex, sn = _line_bruteforce(F[a, b] & 1, (F[a, b] >> (4 + d)) & 1,
-                                                  S[a, b], Uf[a, b, 0], n)
+                newcol, ex, sn, m, an = _line_bruteforce(F[a, b] & 1, (F[a, b] >> (4 + d)) & 1,
+                                                         S[a, b], Uf[a, b, 0], n)
+                merged += m
+                annihilated += an
                 assert np.array_equal(F2[a, b] & 1, newcol)
                 assert np.array_equal(((F2[a, b] >> (4 + d)) & 1).astype(bool), ex)
                 assert np.array_equal(np.where(ex, S2[a, b], 0.0), np.where(ex, sn, 0.0))
+        assert c[3] == merged and c[4] == annihilated
+        total_annihilated += annihilated
+    assert total_annihilated > 0        # the counts are not vacuous
 
 
 # --------------------------------------------------------------------------
