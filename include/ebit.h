@@ -140,6 +140,12 @@ typedef struct {
     int64_t n_interfacial_sum; /* sum of n_interfacial over every ebit_front2vof so far */
     double max_courant;     /* sweeps so far: largest |(dt n) g u| of a marker, in cells (FP32 precision;
                                sec. 2.3 requires <= 1) */
+    int64_t n_annihilated;  /* sweeps so far: aligned edges reached by an even number (>= 2) of markers,
+                               which annihilate (sec. 2.2, Fig. 5a); included in n_merged */
+    int64_t n_ambig_faces;  /* faces of the current state with a marker on each of their four edges
+                               (sec. 2.4: resolved by the face-centre colour) */
+    int64_t n_surrogate;    /* cells the learned surrogate computed in the last ebit_front2vof (0 when it
+                               was not set) */
 } ebit_stats_t;
 
 /*

@@ -101,12 +101,14 @@ constexpr int kSurrWaves = EBIT_SURR_WAVES;   // waves per block of the surrogat
 // totals reduced from the per-wave counters
 enum {
     ST_FALLBACK = 0, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM /* sum of gen * delta */, ST_INTER, ST_AMB,
-    ST_MARK0, ST_MARK1, ST_MARK2, ST_CMAX /* bits of the largest |Courant number| (float) */, ST_COUNT = 16
+    ST_MARK0, ST_MARK1, ST_MARK2, ST_CMAX /* bits of the largest |Courant number| (float) */, ST_ANNIH, ST_SURR,
+    ST_AFACE /* faces with four markers in the current state */, ST_COUNT = 16
 };
 // per-wave counters: cumulative over sweeps / Front2VOF calls, except the
-// last-Front2VOF one (CS_AMB); CS_CMAX holds the bits of a non-negative float
+// last-Front2VOF ones (CS_AMB, CS_SURR); CS_CMAX holds the bits of a non-negative float
 // (ordered like the float) and is reduced by maximum
-enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_GEN, CS_INTER, CS_AMB, CS_CMAX, CS_COUNT };
+enum { CS_FALLBACK = 0, CS_MULTI, CS_CFL, CS_MERGED, CS_ACTIVE, CS_INTER_GEN, CS_INTER, CS_AMB, CS_CMAX, CS_ANNIH,
+       CS_SURR, CS_COUNT };
 
 struct Geo {
     int n;
@@ -951,7 +953,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
                     sdn = clamp_frac<T>((T)v);
                     out |= (uint8_t)(1u << (4 + D));
                 } else if (kl >= 2) {
-                    merged += 1;
+                    merged += 1 + (1 << 16);   // an annihilated pair: counted in the upper half too
                 }
             }
             out |= (uint8_t)(fself & (1u << (1 + D)));   // faces normal to D keep their colour
@@ -1103,7 +1105,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
     // this wave's counters (the wave owns its slot)
     fbc = wave_sum(fbc + fbt);
     cflc = wave_sum(cflc);
-    mergedc = wave_sum(mergedc);
+    // per lane: merges in the lower 16 bits, annihilations in the upper ones
+    // (at most one of each per brick, under 2^15 bricks per wave)
+    const int annc = wave_sum(mergedc >> 16);
+    mergedc = wave_sum(mergedc & 0xFFFF);
     multit = wave_sum(multit);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, off));
@@ -1114,6 +1119,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs<T> &a, const int wv, 
         if (multit) atomicAdd(&a.w.cs[CS_MULTI * nwv + wv], (unsigned long long)multit);
         if (cflc) atomicAdd(&a.w.cs[CS_CFL * nwv + wv], (unsigned long long)cflc);
         if (mergedc) atomicAdd(&a.w.cs[CS_MERGED * nwv + wv], (unsigned long long)mergedc);
+        if (annc) atomicAdd(&a.w.cs[CS_ANNIH * nwv + wv], (unsigned long long)annc);
         if (nact) atomicAdd(&a.w.cs[CS_ACTIVE * nwv + wv], (unsigned long long)nact * 64ull);
         if (cmax > 0.f) atomicMax(&a.w.cs[CS_CMAX * nwv + wv], (unsigned long long)__float_as_uint(cmax));
     }
@@ -1561,7 +1567,10 @@ __device__ __forceinline__ void f2v_wave(const F2VArgs<T> &a, const int classify
             atomicAdd(&a.w.cs[CS_INTER * nwv + wv], (unsigned long long)delta);
             atomicAdd(&a.w.cs[CS_INTER_GEN * nwv + wv], (unsigned long long)((long long)gen * delta));
         }
-        if (!classify) a.w.cs[CS_AMB * nwv + wv] = (unsigned long long)ambc;
+        if (!classify) {
+            a.w.cs[CS_AMB * nwv + wv] = (unsigned long long)ambc;
+            a.w.cs[CS_SURR * nwv + wv] = 0ull;
+        }
     }
 }
 
@@ -1713,12 +1722,15 @@ __global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a)
     const uint32_t total = pre[nc];
     const uint32_t nchunks = (total + 63) / 64;
     const uint32_t gw = gridDim.x * kSurrWaves, gwv = blockIdx.x * kSurrWaves + wave;
-    // the ambiguous-cell slots: one per wave of this grid, the rest zero
+    // the ambiguous- and network-cell slots: one per wave of this grid, the rest zero
     if (blockIdx.x == 0)
-        for (int k = (int)gw + (int)threadIdx.x; k < nc; k += kThreads) a.w.cs[CS_AMB * nc + k] = 0ull;
+        for (int k = (int)gw + (int)threadIdx.x; k < nc; k += kThreads) {
+            a.w.cs[CS_AMB * nc + k] = 0ull;
+            a.w.cs[CS_SURR * nc + k] = 0ull;
+        }
     if (blockIdx.x * kSurrWaves < nchunks) copy_to_lds(&W, &a.w.simg->W, (int)sizeof(MlpWeights));
     __syncthreads();
-    int ambc = 0;
+    int ambc = 0, nsurc = 0;
     for (uint32_t chunk = gwv; chunk < nchunks; chunk += gw) {
         const uint32_t i = chunk * 64 + (uint32_t)lane;
         const bool valid = i < total;
@@ -1746,6 +1758,7 @@ __global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a)
         const bool sur = valid && !amb;
         const unsigned long long bal = __ballot(sur);
         const int nsur = __popcll(bal);
+        nsurc += nsur;
         if (sur) {
             const int pos = __popcll(bal & ((1ull << lane) - 1ull));
             put_features<T>(&xs[wave][pos * kRow1], f, sv);
@@ -1769,7 +1782,10 @@ __global__ __launch_bounds__(64 * kSurrWaves) void k_f2v_b_surr(F2VArgs<T> a)
         wave_sync();
     }
     const int sa = wave_sum(ambc);
-    if (lane == 0 && (int)gwv < nc) a.w.cs[CS_AMB * nc + gwv] = (unsigned long long)sa;
+    if (lane == 0 && (int)gwv < nc) {
+        a.w.cs[CS_AMB * nc + gwv] = (unsigned long long)sa;
+        a.w.cs[CS_SURR * nc + gwv] = (unsigned long long)nsurc;
+    }
 }
 
 // the surrogate's weights image from its FP32 parameters
@@ -1847,7 +1863,7 @@ __global__ __launch_bounds__(256) void k_stats_reduce(Work w, Geo g)
         unsigned long long v = k == CS_CMAX ? max(max(red[k][0], red[k][1]), max(red[k][2], red[k][3]))
                                             : red[k][0] + red[k][1] + red[k][2] + red[k][3];
         const int map[CS_COUNT] = {ST_FALLBACK, ST_MULTI, ST_CFL, ST_MERGED, ST_ACTIVE, ST_INTER_SUM, ST_INTER, ST_AMB,
-                                   ST_CMAX};
+                                   ST_CMAX, ST_ANNIH, ST_SURR};
         w.stat[map[k]] = v;
     }
 }
@@ -1865,12 +1881,14 @@ __device__ __forceinline__ void neumaier_add(double &s, double &c, double v)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_vol_partial(const T *__restrict__ C, const uint8_t *__restrict__ fl, long N,
+__global__ __launch_bounds__(256) void k_vol_partial(const T *__restrict__ C, const uint8_t *__restrict__ fl, int n,
                                                      double *__restrict__ part, unsigned long long *__restrict__ stat)
 {
     __shared__ double ss[256], sc[256];
     double s = 0.0, c = 0.0;
-    int m0 = 0, m1 = 0, m2 = 0;
+    int m0 = 0, m1 = 0, m2 = 0, af = 0;
+    const uint32_t un = (uint32_t)n, unn = un * un;
+    const long N = (long)unn * n;
     long stride = (long)gridDim.x * blockDim.x;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += stride) {
         neumaier_add(s, c, (double)C[q]);
@@ -1878,6 +1896,17 @@ __global__ __launch_bounds__(256) void k_vol_partial(const T *__restrict__ C, co
         m0 += (f >> 4) & 1;
         m1 += (f >> 5) & 1;
         m2 += (f >> 6) & 1;
+        // faces whose lowest corner is this node with a marker on each of their
+        // four edges (sec. 2.4's face ambiguity), one family per normal axis
+        if (f & 0x70) {
+            const uint32_t uq = (uint32_t)q, x = uq % un, y = (uq / un) % un, z = uq / unn;
+            const uint8_t fx = fl[uq + (x + 1 == un ? 0u - (un - 1) : 1u)];
+            const uint8_t fy = fl[uq + (y + 1 == un ? 0u - (un - 1) * un : un)];
+            const uint8_t fz = fl[uq + (z + 1 == un ? 0u - (un - 1) * unn : unn)];
+            af += (f >> 5) & (fz >> 5) & (f >> 6) & (fy >> 6) & 1;   // normal x: y-edges, z-edges
+            af += (f >> 4) & (fz >> 4) & (f >> 6) & (fx >> 6) & 1;   // normal y: x-edges, z-edges
+            af += (f >> 4) & (fy >> 4) & (f >> 5) & (fx >> 5) & 1;   // normal z: x-edges, y-edges
+        }
     }
     ss[threadIdx.x] = s;
     sc[threadIdx.x] = c;
@@ -1900,11 +1929,13 @@ __global__ __launch_bounds__(256) void k_vol_partial(const T *__restrict__ C, co
         m0 += __shfl_down(m0, off);
         m1 += __shfl_down(m1, off);
         m2 += __shfl_down(m2, off);
+        af += __shfl_down(af, off);
     }
     if ((threadIdx.x & 63) == 0) {
         if (m0) atomicAdd(&stat[ST_MARK0], (unsigned long long)m0);
         if (m1) atomicAdd(&stat[ST_MARK1], (unsigned long long)m1);
         if (m2) atomicAdd(&stat[ST_MARK2], (unsigned long long)m2);
+        if (af) atomicAdd(&stat[ST_AFACE], (unsigned long long)af);
     }
 }
 
@@ -1976,6 +2007,7 @@ __global__ void k_err_final(double *part, int nblocks)
 __global__ void k_zero_marks(unsigned long long *stat)
 {
     if (threadIdx.x < 3) stat[ST_MARK0 + threadIdx.x] = 0;
+    if (threadIdx.x == 3) stat[ST_AFACE] = 0;
 }
 
 }  // namespace
@@ -2371,15 +2403,14 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
 {
     if (!c || !C || !out) return EBIT_EINVAL;
     hipStream_t st = S(stream);
-    long N = (long)c->n * c->n * c->n;
     hipLaunchKernelGGL(k_zero_marks, dim3(1), dim3(64), 0, st, c->w.stat);
     hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, c->w, c->g);
     if (c->precision == EBIT_FP64)
         hipLaunchKernelGGL(k_vol_partial<double>, dim3(kRedBlocks - 1), dim3(256), 0, st, (const double *)C,
-                           c->flags[c->cur], N, c->w.part, c->w.stat);
+                           c->flags[c->cur], c->n, c->w.part, c->w.stat);
     else
         hipLaunchKernelGGL(k_vol_partial<float>, dim3(kRedBlocks - 1), dim3(256), 0, st, (const float *)C,
-                           c->flags[c->cur], N, c->w.part, c->w.stat);
+                           c->flags[c->cur], c->n, c->w.part, c->w.stat);
     hipLaunchKernelGGL(k_vol_final, dim3(1), dim3(64), 0, st, c->w.part, kRedBlocks - 1);
     int rc = check_launch();
     if (rc != EBIT_OK) return rc;
@@ -2402,6 +2433,9 @@ int ebit_stats(ebit_ctx *c, const void *C, ebit_stats_t *out, void *stream)
     out->n_cfl = (int64_t)stat[ST_CFL];
     out->n_merged = (int64_t)stat[ST_MERGED];
     out->n_active_cells = (int64_t)stat[ST_ACTIVE];
+    out->n_annihilated = (int64_t)stat[ST_ANNIH];
+    out->n_ambig_faces = (int64_t)stat[ST_AFACE];
+    out->n_surrogate = c->fgen > 1 ? (int64_t)stat[ST_SURR] : 0;
     out->step_sweeps = (int64_t)(c->t - 2);
     // count after generation j: S1(j) = sum of delta up to j; summed over the
     // generations 1..K so far: (K + 1) S1 - sum of j delta_j

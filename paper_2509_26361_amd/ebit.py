@@ -61,6 +61,9 @@ class Stats(ctypes.Structure):
         ("step_sweeps", ctypes.c_int64),
         ("n_interfacial_sum", ctypes.c_int64),
         ("max_courant", ctypes.c_double),
+        ("n_annihilated", ctypes.c_int64),
+        ("n_ambig_faces", ctypes.c_int64),
+        ("n_surrogate", ctypes.c_int64),
     ]
 
     def as_dict(self):

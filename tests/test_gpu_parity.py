@@ -49,6 +49,20 @@ def compare_state(e, st, tol=TOL, what=""):
         assert d <= tol, f"{what}: s[{k}] differs by {d}"
 
 
+def four_marker_faces(flags):
+    """Faces with a marker on each of their four edges (sec. 2.4), counted
+    by brute force on a (z, y, x) flags array: a face is named by its lowest
+    corner and its normal axis; its edges run along the two other axes from
+    that corner and from the corner one step along the other of them."""
+    m = [((flags >> (4 + e)) & 1).astype(bool) for e in range(3)]   # marker on the edge along x, y, z
+    step = lambda a, e: np.roll(a, -1, axis=2 - e)                  # value at the node one step along e
+    total = 0
+    for nrm in range(3):
+        a, b = [e for e in range(3) if e != nrm]
+        total += int((m[a] & step(m[a], b) & m[b] & step(m[b], a)).sum())
+    return total
+
+
 def compare_C(C, Co, tol=TOL, what=""):
     torch.cuda.synchronize()
     d = np.max(np.abs(C.cpu().numpy().astype(np.float64) - Co))
@@ -87,8 +101,9 @@ def test_single_sweep_parity_random_states(seed, full):
         compare_C(C, Co, TOL, f"seed {seed} dir {d}")
         s = e.stats(C)
         assert s["n_fallback"] == cnt[0] and s["n_multi"] == cnt[1]
-        assert s["n_cfl"] == cnt[2] and s["n_merged"] == cnt[3]
+        assert s["n_cfl"] == cnt[2] and s["n_merged"] == cnt[3] and s["n_annihilated"] == cnt[4]
         assert s["n_interfacial"] == O.count_interfacial(st2)
+        assert s["n_ambig_faces"] == four_marker_faces(st2.flags)
         assert s["n_ambiguous"] == int(amb.sum())
 
 

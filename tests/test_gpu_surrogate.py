@@ -104,10 +104,12 @@ def check_in_front2vof(e, n, theta, vol_tol):
     number of ambiguous cells."""
     Cg = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
     e.front2vof(Cg)
+    assert e.stats(Cg)["n_surrogate"] == 0
     Xr, cr = e.dataset()
     e.set_surrogate(theta)
     Cs = torch.zeros_like(Cg)
-    e.front2vof(Cs)
+    e.front2vof(Cs)                                           # a new C: every cell recomputed
+    n_surrogate = e.stats(Cs)["n_surrogate"]
     e.set_surrogate(None)
     fl, s = e.state()
     st = O.State(n, fl.cpu().numpy(), [x.cpu().numpy() for x in s])
@@ -119,6 +121,7 @@ def check_in_front2vof(e, n, theta, vol_tol):
     assert np.array_equal(Cs_[amb], Cg_[amb])                 # ambiguous cells: geometric
     y = E.mlp_forward(theta, Xr).double().cpu().numpy()
     assert np.array_equal(np.sort(Cs_[inter & ~amb]), np.sort(y))   # the others: the network
+    assert n_surrogate == int((inter & ~amb).sum()) == len(y)
     vg, vs = Cg_.sum(), Cs_.sum()
     print(f"n={n}: {int(amb.sum())} ambiguous, {int(inter.sum())} interfacial; volume geometric {vg:.3f}, "
           f"surrogate {vs:.3f}, rel diff {abs(vs - vg) / vg:.2e}")
