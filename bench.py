@@ -324,7 +324,8 @@ def main():
         "interfacial_cells": {"start": st0["n_interfacial"], "end": st1["n_interfacial"],
                               "mean": n_start / K},
         "volume": {"start": st0["volume"] + st0["volume_comp"], "end": st1["volume"] + st1["volume_comp"]},
-        "counters": {k: st1[k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged", "max_courant")},
+        "counters": {k: st1[k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged", "n_annihilated",
+                                         "n_ambig_faces", "max_courant")},
         "band_bricks_per_sweep": (st1["n_active_cells"] - st0["n_active_cells"]) / 64.0 / (3 * K),
         "coupling_kernels": coupling,
     }
@@ -361,7 +362,9 @@ def main():
             qb = run_case(E, I, torch, n, "fp32", W, K, events=True, theta=theta, every=every)
             sf = {"value": q["n_start"] / q["wall"], "ms_per_step": q["wall"] / K * 1e3,
                   "launch_us": {k: (qb["kt"][k][1] / qb["kt"][k][0] * 1e6 if qb["kt"][k][0] else None)
-                                for k in qb["kt"]}, "training": info}
+                                for k in qb["kt"]}, "training": info,
+                  # the last Front2VOF's cells: computed by the network, and geometric ambiguous ones
+                  "cells_last_front2vof": {"surrogate": q["st1"]["n_surrogate"], "ambiguous": q["st1"]["n_ambiguous"]}}
             g = accuracy_run(E, I, torch, n, "fp32", theta=theta)
             Cs = g.pop("C")
             g.update(form_vs_fp64(g, ref, Cs, C64))
@@ -548,7 +551,8 @@ def run_mixed(a, E, I, torch):
         "timing_pass": {"ms_per_step_with_events": wall_events / K * 1e3, "every": every},
         "interfacial_cells": {"start": r["st0"]["n_interfacial"], "end": r["st1"]["n_interfacial"], "mean": units},
         "volume": {"start": r["st0"]["volume"] + r["st0"]["volume_comp"], "end": V64},
-        "counters": {k: r["st1"][k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged")},
+        "counters": {k: r["st1"][k] for k in ("n_fallback", "n_multi", "n_cfl", "n_merged", "n_annihilated",
+                                              "n_ambig_faces")},
     }
     C64 = r["C"]
     del r
@@ -571,6 +575,7 @@ def run_mixed(a, E, I, torch):
                      "max_abs_C_diff_vs_fp64": float((q["C"].double() - C64).abs().max())}
         if surr:
             out[name]["ambiguous_cells_end"] = q["st1"]["n_ambiguous"]
+            out[name]["surrogate_cells_end"] = q["st1"]["n_surrogate"]
             out[name]["training"] = surr[1]
         del q
         torch.cuda.empty_cache()
